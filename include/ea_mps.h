@@ -1,0 +1,198 @@
+/*
+ * ea_mps.h -- C ABI of the entanglement-aware MPS / MPO gate-update library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Oliva, "An entanglement-aware quantum computer simulation
+ * algorithm" (arXiv:2307.16870).  A pure state is a matrix product state
+ * (Sec. II, Eq. 2); a mixed state is a matrix product operator (Sec. II,
+ * Eq. 4).  The state is kept in mixed canonical form with one orthogonality
+ * centre (Sec. III).  A two-qubit gate contracts the two neighbouring site
+ * tensors with the gate, takes the SVD, keeps the fewest singular values
+ * whose kept weight sum_kept s^2 / sum_all s^2 reaches the bond's target
+ * truncation fidelity (Sec. V, Eqs. 10-11; rule of Sec. VI), and multiplies
+ * the achieved truncation fidelity into the running estimate of the state
+ * fidelity (Sec. VI, Eq. 12).  Targets come from F_min (Eq. 14 and the
+ * adaptive updates of Sec. VI); an optional cap on the bond dimension
+ * overrides them (end of Sec. VI).
+ *
+ * Conventions
+ *   - Sites are 0-based; qubit 0 is the most significant bit of a state-vector
+ *     index.  Site tensor i has shape (chi_i, d, chi_{i+1}), row-major,
+ *     chi_0 = chi_N = 1; d = 2 (EA_PURE) or d = 4 (EA_MIXED, p = 2s + s' for
+ *     |s><s'|).
+ *   - Every complex number crossing this ABI is two doubles (re, im),
+ *     interleaved, layout-compatible with C99 `double _Complex`.
+ *   - One-site operators are d x d, row-major.  Two-site operators on
+ *     (i, i+1) are d^2 x d^2, row-major, indexed [d*s_i + s_{i+1},
+ *     d*t_i + t_{i+1}]; for EA_MIXED that is the 16x16 superoperator with
+ *     p_i = 2 s_i + s_i'.
+ *   - All pointers in this header are HOST pointers unless stated otherwise.
+ *     The caller owns them; the library copies what it needs before the call
+ *     returns.  Device memory of the state is owned by the library.
+ *
+ * Errors
+ *   Return value 0 (EA_OK) is success, > 0 a warning (the update was applied),
+ *   < 0 an error.  Arguments are validated on the host before anything is
+ *   enqueued; on an error the state is unchanged, except after EA_EHIP (a HIP
+ *   runtime failure), which poisons the handle: every later call on it
+ *   returns EA_EHIP.  ea_last_error() returns a thread-local message for the
+ *   last non-zero status.
+ *
+ * Threading: one handle must not be used from two threads at once; distinct
+ * handles are independent.  Calls are enqueued on the handle's HIP stream;
+ * calls that return host data synchronise that stream.
+ */
+#ifndef EA_MPS_H
+#define EA_MPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ea_mps ea_mps; /* opaque handle, owned by the library */
+
+enum ea_kind { EA_PURE = 0, EA_MIXED = 1 };
+
+/* Arithmetic of the state and of the update.
+ * EA_C128: complex FP64 everywhere.
+ * EA_C64:  complex FP32 storage, contraction and Jacobi rotations; singular
+ *          values, the kept-weight search and the fidelity product in FP64.
+ * EA_C64_BF16X3: as EA_C64, with the two-site contraction done as three
+ *          BF16 products per real product (x = hi + lo; hi*hi + hi*lo +
+ *          lo*hi) with FP32 accumulation. */
+enum ea_prec { EA_C128 = 0, EA_C64 = 1, EA_C64_BF16X3 = 2 };
+
+enum ea_status {
+    EA_OK = 0,
+    EA_WARN_CAPPED = 1, /* chi_max bound: target truncation fidelity not met */
+    EA_WARN_NOCONV = 2, /* Jacobi stopped at max_sweeps */
+    EA_EINVAL = -1,     /* bad argument */
+    EA_ERANGE = -2,     /* site index out of range */
+    EA_ENOMEM = -3,     /* device allocation failed */
+    EA_EHIP = -4,       /* HIP runtime error; handle poisoned */
+    EA_ETOOBIG = -5     /* output buffer too small / N too large */
+};
+
+enum ea_strategy { EA_NAIVE = 0, EA_GLOBAL = 1, EA_NEAREST = 2 };
+
+enum ea_option {
+    EA_OPT_JACOBI_TOL = 0,   /* rotate a pair if |g| > tol*sqrt(a b); default m*eps */
+    EA_OPT_MAX_SWEEPS = 1,   /* default 40 */
+    EA_OPT_TAU = 2,          /* numerical-zero cutoff tau*s_0; 1e-13 (FP64), 2e-6 (FP32) */
+    EA_OPT_BLOCK = 3,        /* Jacobi column-block width (0 = automatic) */
+    EA_OPT_CHI_MAX = 4       /* cap on kept rank; 0 = none */
+};
+
+/* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */
+typedef struct ea_gate_record {
+    int64_t gate;    /* 0-based index among two-qubit updates */
+    int32_t site;    /* left site */
+    int32_t chi_l, chi_m, chi_r; /* bonds before the update */
+    int32_t k;       /* kept rank = new chi_m */
+    int32_t k_f;     /* rank asked for by the target alone */
+    int32_t sweeps;  /* Jacobi sweeps used */
+    int32_t capped;  /* 1 if chi_max bound */
+    double f_t;      /* target truncation fidelity */
+    double f;        /* achieved truncation fidelity 1 - D(k)/T */
+    double total;    /* T = sum of all s^2 */
+    double lnP;      /* running log fidelity estimate after this update */
+} ea_gate_record;
+
+/* Create a product state (Sec. VI: simulations start from a product state).
+ *  n_sites >= 1; kind: ea_kind; prec: ea_prec; chi_max: cap on the kept rank
+ *  (0 = no cap, end of Sec. VI).
+ *  local: NULL for |0...0> (pure) or |0><0|^N (mixed), else n_sites*d complex
+ *  numbers, the d-vector of each site (vec(rho_i) for EA_MIXED).
+ *  hip_stream: hipStream_t on which all work is enqueued (NULL = null stream).
+ *  out: receives the handle.  Returns EA_EINVAL on bad arguments, EA_ENOMEM if
+ *  device memory cannot be allocated. */
+int mps_init_product(int n_sites, int kind, int prec, int chi_max,
+                     const double *local, void *hip_stream, ea_mps **out);
+
+/* Release the handle and all its device memory.  NULL is ignored. */
+void mps_free(ea_mps *h);
+
+/* Tuning and numerical options (ea_option).  EA_EINVAL on unknown option or
+ * out-of-range value. */
+int mps_set_option(ea_mps *h, int option, double value);
+
+/* Target schedule (Sec. VI): F_min in (0, 1], n_2q_total >= 1 two-qubit gates
+ * to come, strategy ea_strategy: naive f_t = F_min^(1/n) (Eq. 14); global
+ * f_t = (F_min / P)^(1/(n - g)) before gate g; nearest f_t = F_min^((g+1)/n)
+ * / P.  Targets are clamped to (0, 1].  Without a schedule every target is 1
+ * (only numerically zero singular values are dropped). */
+int mps_set_schedule(ea_mps *h, double f_min, long n_2q_total, int strategy);
+
+/* One-site operator (Sec. II: one-qubit gates do not change bond dimensions).
+ *  op: d x d complex (2x2 unitary, or 4x4 superoperator for EA_MIXED).
+ *  A non-unitary operator first moves the orthogonality centre to `site`. */
+int mps_apply_1q(ea_mps *h, int site, const double *op);
+
+/* Two-site update on (site, site+1) (Sec. V-VI).
+ *  op: d^2 x d^2 complex gate / superoperator.
+ *  fidelity_budget: target truncation fidelity f_t in (0, 1]; a negative
+ *  value takes the next target from the schedule.
+ *  f_out: if non-NULL receives the achieved truncation fidelity.
+ *  The centre ends on site+1.  Returns EA_WARN_CAPPED if chi_max bound. */
+int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget,
+                 double *f_out);
+
+/* A layer of two-site updates on disjoint pairs (sites[j], sites[j]+1).
+ *  ops: n_gates consecutive d^2 x d^2 complex matrices.
+ *  budgets: NULL (schedule) or n_gates targets, one per gate in the order
+ *  given.  Gates are visited in increasing site order if the centre is
+ *  nearer the lowest site, else in decreasing order; the centre follows.
+ *  f_out: NULL or n_gates achieved fidelities, in the order given.
+ *  EA_EINVAL if two pairs overlap; then nothing is applied. */
+int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
+                    const double *budgets, double *f_out);
+
+/* Running estimate of the state fidelity, prod_i f_i (Eq. 12; Eq. 13 for
+ * noisy runs, where it is a lower estimate).  Either pointer may be NULL. */
+int mps_fidelity_estimate(const ea_mps *h, double *F_out, double *lnF_out);
+
+/* Expectation values (Sec. III, Eqs. 5-6).  Term j acts on sites[j]
+ * (widths[j] = 1, d x d operator) or (sites[j], sites[j]+1) (widths[j] = 2,
+ * 4x4 operator on the two qubits, NOT a superoperator).  ops: the operators
+ * concatenated.  out: n_terms complex values.  Pure: <psi|O|psi>/<psi|psi>
+ * from the centre block (the centre is moved).  Mixed: Tr(rho O)/Tr(rho). */
+int mps_expect(ea_mps *h, int n_terms, const int *sites, const int *widths,
+               const double *ops, double *out);
+
+/* Dense output (Eq. 1 / Eq. 3).  Pure: the 2^N amplitudes (N <= 28),
+ * out_complex_len >= 2^N.  Mixed: rho / Tr(rho) as a row-major 2^N x 2^N
+ * matrix (N <= 13), out_complex_len >= 4^N.  EA_ETOOBIG otherwise. */
+int mps_to_statevector(ea_mps *h, double *out, size_t out_complex_len);
+
+/* Bond dimensions chi_1 .. chi_{N-1} into out (n_sites - 1 ints). */
+int mps_bond_dims(const ea_mps *h, int *out);
+
+/* Current orthogonality centre (site index). */
+int mps_center(const ea_mps *h, int *out);
+
+/* Copy the per-update records (oldest first).  n_out receives the number of
+ * records available; at most `cap` are written. */
+int mps_gate_log(const ea_mps *h, ea_gate_record *records, size_t cap, size_t *n_out);
+
+/* Replace the whole state by explicit site tensors (checkpoint restore and
+ * tests).  bond_dims: n_sites+1 ints with both ends 1.  data: the site
+ * tensors concatenated, complex, each (chi_i, d, chi_{i+1}) row-major.
+ * center: orthogonality centre the caller vouches for.  The fidelity log,
+ * estimate and gate counter are left as they are. */
+int mps_load(ea_mps *h, const int *bond_dims, const double *data, int center);
+
+/* Copy site tensor `site` (chi_l*d*chi_r complex) into out; dims receives
+ * (chi_l, d, chi_r).  EA_ETOOBIG if out_complex_len is too small. */
+int mps_get_site(ea_mps *h, int site, double *out, size_t out_complex_len, int *dims);
+
+/* Message for the last non-zero status returned on this thread. */
+const char *ea_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EA_MPS_H */

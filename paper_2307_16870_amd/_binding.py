@@ -1,0 +1,212 @@
+"""ctypes binding of ``libeamps.so`` (declared in include/ea_mps.h).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name, converting NumPy arrays to interleaved complex doubles.  All
+arithmetic of the gate update runs in the library's HIP kernels; if the
+library is missing this module raises at import time.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libeamps.so")
+
+EA_PURE, EA_MIXED = 0, 1
+EA_C128, EA_C64, EA_C64_BF16X3 = 0, 1, 2
+EA_OK, EA_WARN_CAPPED, EA_WARN_NOCONV = 0, 1, 2
+EA_EINVAL, EA_ERANGE, EA_ENOMEM, EA_EHIP, EA_ETOOBIG = -1, -2, -3, -4, -5
+EA_NAIVE, EA_GLOBAL, EA_NEAREST = 0, 1, 2
+EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
+
+SYMBOLS = [
+    "mps_init_product", "mps_free", "mps_set_option", "mps_set_schedule", "mps_apply_1q",
+    "mps_apply_2q", "mps_apply_layer", "mps_fidelity_estimate", "mps_expect",
+    "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
+    "mps_get_site", "ea_last_error",
+]
+
+
+class EAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class GateRecord(ct.Structure):
+    _fields_ = [("gate", ct.c_int64), ("site", ct.c_int32), ("chi_l", ct.c_int32),
+                ("chi_m", ct.c_int32), ("chi_r", ct.c_int32), ("k", ct.c_int32),
+                ("k_f", ct.c_int32), ("sweeps", ct.c_int32), ("capped", ct.c_int32),
+                ("f_t", ct.c_double), ("f", ct.c_double), ("total", ct.c_double),
+                ("lnP", ct.c_double)]
+
+
+def load_library(path: str = LIB_PATH) -> ct.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2307_16870_amd._build`")
+    lib = ct.CDLL(path)
+    P, I, D, L, S = ct.c_void_p, ct.c_int, ct.c_double, ct.c_long, ct.c_size_t
+    dp, ip = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)
+    sig = {
+        "mps_init_product": (I, [I, I, I, I, dp, P, ct.POINTER(P)]),
+        "mps_free": (None, [P]),
+        "mps_set_option": (I, [P, I, D]),
+        "mps_set_schedule": (I, [P, D, L, I]),
+        "mps_apply_1q": (I, [P, I, dp]),
+        "mps_apply_2q": (I, [P, I, dp, D, dp]),
+        "mps_apply_layer": (I, [P, I, ip, dp, dp, dp]),
+        "mps_fidelity_estimate": (I, [P, dp, dp]),
+        "mps_expect": (I, [P, I, ip, ip, dp, dp]),
+        "mps_to_statevector": (I, [P, dp, S]),
+        "mps_bond_dims": (I, [P, ip]),
+        "mps_center": (I, [P, ip]),
+        "mps_gate_log": (I, [P, ct.POINTER(GateRecord), S, ct.POINTER(S)]),
+        "mps_load": (I, [P, ip, dp, I]),
+        "mps_get_site": (I, [P, I, dp, S, ip]),
+        "ea_last_error": (ct.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def _c(a) -> np.ndarray:
+    """Interleaved complex128 view (contiguous copy if needed)."""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _dp(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_int))
+
+
+def _chk(rc: int) -> int:
+    if rc < 0:
+        raise EAError(rc, _lib.ea_last_error().decode())
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):  # torch.cuda.Stream
+        return ct.c_void_p(stream.cuda_stream)
+    return ct.c_void_p(int(stream))
+
+
+def ea_last_error() -> str:
+    return _lib.ea_last_error().decode()
+
+
+def mps_init_product(n_sites, kind=EA_PURE, prec=EA_C128, chi_max=0, local=None, stream=None):
+    h = ct.c_void_p()
+    loc = None
+    if local is not None:
+        loc = _c(local)
+    _chk(_lib.mps_init_product(int(n_sites), int(kind), int(prec), int(chi_max),
+                               _dp(loc) if loc is not None else None,
+                               _stream_handle(stream), ct.byref(h)))
+    return h
+
+
+def mps_free(h):
+    _lib.mps_free(h)
+
+
+def mps_set_option(h, option, value):
+    return _chk(_lib.mps_set_option(h, int(option), float(value)))
+
+
+def mps_set_schedule(h, f_min, n_2q_total, strategy=EA_GLOBAL):
+    return _chk(_lib.mps_set_schedule(h, float(f_min), int(n_2q_total), int(strategy)))
+
+
+def mps_apply_1q(h, site, op):
+    o = _c(op)
+    return _chk(_lib.mps_apply_1q(h, int(site), _dp(o)))
+
+
+def mps_apply_2q(h, site, op, fidelity_budget=-1.0):
+    """Returns (status, achieved f)."""
+    o = _c(op)
+    f = ct.c_double(0.0)
+    rc = _chk(_lib.mps_apply_2q(h, int(site), _dp(o), float(fidelity_budget), ct.byref(f)))
+    return rc, f.value
+
+
+def mps_apply_layer(h, sites, ops, budgets=None):
+    """Returns (status, achieved f per gate in the order given)."""
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int32))
+    o = _c(np.stack([np.asarray(x) for x in ops]) if isinstance(ops, (list, tuple)) else ops)
+    b = None if budgets is None else np.ascontiguousarray(np.asarray(budgets, dtype=np.float64))
+    f = np.zeros(len(s))
+    rc = _chk(_lib.mps_apply_layer(h, len(s), _ip(s), _dp(o), _dp(b) if b is not None else None,
+                                   _dp(f)))
+    return rc, f
+
+
+def mps_fidelity_estimate(h):
+    F, lnF = ct.c_double(), ct.c_double()
+    _chk(_lib.mps_fidelity_estimate(h, ct.byref(F), ct.byref(lnF)))
+    return F.value, lnF.value
+
+
+def mps_expect(h, sites, widths, ops):
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int32))
+    w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    o = _c(np.concatenate([np.asarray(x, dtype=np.complex128).ravel() for x in ops]))
+    out = np.zeros(len(s), dtype=np.complex128)
+    _chk(_lib.mps_expect(h, len(s), _ip(s), _ip(w), _dp(o), _dp(out)))
+    return out
+
+
+def mps_to_statevector(h, n_complex):
+    out = np.zeros(n_complex, dtype=np.complex128)
+    _chk(_lib.mps_to_statevector(h, _dp(out), out.size))
+    return out
+
+
+def mps_bond_dims(h, n_sites):
+    out = np.zeros(n_sites - 1, dtype=np.int32)
+    _chk(_lib.mps_bond_dims(h, _ip(out)))
+    return out.tolist()
+
+
+def mps_center(h):
+    c = ct.c_int()
+    _chk(_lib.mps_center(h, ct.byref(c)))
+    return c.value
+
+
+def mps_gate_log(h):
+    n = ct.c_size_t()
+    _chk(_lib.mps_gate_log(h, None, 0, ct.byref(n)))
+    recs = (GateRecord * max(1, n.value))()
+    _chk(_lib.mps_gate_log(h, recs, n.value, ct.byref(n)))
+    return [{f: getattr(r, f) for f, _ in GateRecord._fields_} for r in recs[: n.value]]
+
+
+def mps_load(h, tensors, center):
+    dims = [tensors[0].shape[0]] + [t.shape[2] for t in tensors]
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+    data = _c(np.concatenate([np.asarray(t, dtype=np.complex128).ravel() for t in tensors]))
+    return _chk(_lib.mps_load(h, _ip(d), _dp(data), int(center)))
+
+
+def mps_get_site(h, site):
+    dims = np.zeros(3, dtype=np.int32)
+    _chk(_lib.mps_get_site(h, int(site), None, 0, _ip(dims)))
+    out = np.zeros(int(np.prod(dims)), dtype=np.complex128)
+    _chk(_lib.mps_get_site(h, int(site), _dp(out), out.size, _ip(dims)))
+    return out.reshape(tuple(int(x) for x in dims))

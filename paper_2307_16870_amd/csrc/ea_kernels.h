@@ -1,0 +1,118 @@
+// Host-visible launchers of the HIP kernels (one instantiation per precision).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+// Result of one truncation decision, written by the device, read by the host.
+struct ea_dev_rec {
+    int k;        // kept rank
+    int k_f;      // rank asked for by the target alone
+    int k_nz;     // number of singular values above tau * s_0
+    int capped;   // chi_max bound
+    int sweeps;   // Jacobi sweeps (Gram evaluations) used
+    int converged;
+    int r;        // number of singular values
+    int pad;
+    double total;    // T = sum s^2
+    double disc;     // D(k) = sum_{j>=k} s_j^2
+    double f;        // 1 - D(k)/T
+    double lnf;      // log1p(-D(k)/T)
+    double kept2;    // T - D(k)
+    double scale;    // 1/sqrt(kept2) for an update, 1 for a centre move
+    double s0;       // largest singular value
+    double pad2;
+};
+
+// Largest number of singular values the single-workgroup sort handles.
+constexpr int EA_SORT_MAX = 4096;
+
+// ---- contraction / small dense kernels (T = float or double) -------------
+// Theta[(l,s1),(s2,r)] = sum G[(s1 s2),(t1 t2)] sum_m A[l,t1,m] B[m,t2,r].
+// orient 0: W column-major (dchiL x dchiR), W[col*dchiL+row] = Theta.
+// orient 1: W = Theta^H column-major, W[row*dchiR+col] = conj(Theta).
+template <typename T>
+void launch_theta(const void *A, const void *B, const void *G, void *W, int chiL, int chiM,
+                  int chiR, int d, int orient, hipStream_t s);
+// C (M x N) = A (M x K) * B (K x N), row-major with leading dimensions.
+template <typename T>
+void launch_gemm(const void *A, const void *B, void *C, int M, int N, int K, int lda, int ldb,
+                 int ldc, hipStream_t s);
+// out[l,s,r] = sum_t g[s,t] in[l,t,r]  (in == out allowed).
+template <typename T>
+void launch_apply1(const void *in, void *out, const void *g, int chiL, int d, int chiR,
+                   hipStream_t s);
+// V = identity (n x n).
+template <typename T>
+void launch_eye(void *V, int n, hipStream_t s);
+// out (column-major M x N) = in (row-major M x N), optionally conjugated
+// elementwise without transposition (conj_copy = 1: out[i] = conj(in[i])).
+template <typename T>
+void launch_to_colmajor(const void *in, void *out, int M, int N, int conj_copy, hipStream_t s);
+// s_out[j] = || column j || (FP64 accumulation), column-major m x n.
+template <typename T>
+void launch_colnorms(const void *W, int m, int n, double *s_out, hipStream_t s);
+// Write-back gather: for j < k, alpha_j = s_j^es * scale^ec;
+//   rows_out:  out[j*X + x] = alpha_j * op(src[perm[j]*ld + x])
+//   transposed: out[x*k + j] = alpha_j * op(src[perm[j]*ld + x])
+template <typename T>
+void launch_gather(const void *src, int ld, const int *perm, const double *s_sorted,
+                   const ea_dev_rec *rec, int k, int X, int conj_src, int es, int ec,
+                   int transposed, void *out, hipStream_t s);
+// Convert T -> double complex.
+template <typename T>
+void launch_to_c128(const void *in, double *out, size_t n, hipStream_t s);
+template <typename T>
+void launch_from_c128(const double *in, void *out, size_t n, hipStream_t s);
+// Fill n ints with a value (graph-capturable replacement of a memset).
+void launch_fill_int(int *p, int n, int v, hipStream_t s);
+
+// ---- truncation -----------------------------------------------------------
+// mode 0: truncation rule of the two-site update; mode 1: centre move (keep
+// all numerically non-zero values, no renormalisation).  forced_k > 0 forces
+// the kept rank.  chi_max <= 0: no cap.
+void launch_sort_trunc(const double *s_raw, int r, double f_t, int chi_max, double tau,
+                       int mode, int forced_k, const int *sweeps_dev, int *perm,
+                       double *s_sorted, ea_dev_rec *rec, hipStream_t s);
+
+// ---- one-sided block Jacobi ----------------------------------------------
+// Single-workgroup form for n <= 64 columns: iterates to convergence.
+// sweeps_dev[0] = Gram evaluations, sweeps_dev[1] = converged flag.
+template <typename T>
+void launch_jacobi_single(void *W, int m, void *V, int n, double tol, int inner_max,
+                          int max_sweeps, int *sweeps_dev, hipStream_t s);
+// One round of the block round-robin ordering: nb blocks of width w,
+// nb/2 workgroups; adds the number of rotated pairs to *rot_counter.
+// ncmax selects the instantiation (2w <= ncmax).
+template <typename T>
+void launch_jacobi_round(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
+                         int inner_max, int ncmax, int *rot_counter, hipStream_t s);
+
+// ---- observables ----------------------------------------------------------
+// partial[blk] = (sum conj(a) b, sum |a|^2) over len elements; then
+// launch_cdot_final sums the partials in fixed order into out[0..2]
+// (re, im, norm).
+template <typename T>
+int launch_cdot(const void *a, const void *b, size_t len, double *partial, int max_blocks,
+                hipStream_t s);
+void launch_cdot_final(const double *partial, int nblk, double *out, hipStream_t s);
+// Mixed-state transfer vectors.
+// out[r] = sum_{l,p} env[l] wgt[p] A[l,p,r]
+template <typename T>
+void launch_env_left(const void *env, const void *A, const void *wgt, void *out, int chiL,
+                     int d, int chiR, hipStream_t s);
+// out[l] = sum_{p,r} A[l,p,r] wgt[p] env[r]
+template <typename T>
+void launch_env_right(const void *A, const void *wgt, const void *env, void *out, int chiL,
+                      int d, int chiR, hipStream_t s);
+// Two-site weighted transfer: out[r] = sum env[l] A[l,p,m] W[p,q] B[m,q,r]
+// via tmp[p,m] = sum_l env[l] A[l,p,m].
+template <typename T>
+void launch_env_left2(const void *env, const void *A, const void *B, const void *W2,
+                      void *tmp, void *out, int chiL, int d, int chiM, int chiR,
+                      hipStream_t s);
+// vec over (p_1..p_N), p = 2 s + s', to rho[s..., s'...] (2^N x 2^N).
+template <typename T>
+void launch_vec_to_rho(const void *vec, void *rho, int n, hipStream_t s);
+// x[i] *= (re + i im), i < n.
+template <typename T>
+void launch_scale(void *x, size_t n, double re, double im, hipStream_t s);

@@ -1,0 +1,240 @@
+// One-sided (Hestenes) block Jacobi SVD of a column-major matrix W (m x n,
+// m >= n), accumulating the right rotations in V (n x n, column-major).
+//
+// A workgroup owns a set of nc <= NC columns (one block pair of the
+// round-robin ordering, or all columns when n <= 64).  It forms their Gram
+// matrix G = W_c^H W_c in LDS, diagonalises G by two-sided Jacobi rotations
+// (each rotation is the one-sided rotation of the corresponding column pair
+// expressed on the Gram matrix: the symmetric 2x2 Schur rotation of
+// [[a, |g|], [|g|, b]] after removing the phase of g), accumulates them in J,
+// and finally applies W_c <- W_c J and V_c <- V_c J.  The next Gram is
+// formed from the rotated columns again, so the accuracy is that of
+// one-sided Jacobi, not of an eigen-solve of a squared matrix.
+// A pair (p, q) is rotated when |G_pq| > tol * sqrt(G_pp G_qq); the number of
+// pairs rotated on the first inner sweep of a freshly formed Gram matrix is
+// the convergence measure (0 over a full outer sweep = converged).
+#include "ea_dev.h"
+#include "ea_kernels.h"
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_jacobi_block(cx<T> *__restrict__ W, int m,
+                                                      cx<T> *__restrict__ V, int n, int w,
+                                                      int nb, int rnd, T tol, int inner_max,
+                                                      int single, int max_outer,
+                                                      int *__restrict__ rot_counter,
+                                                      int *__restrict__ sweeps_out) {
+    constexpr int RC = (NC >= 64 && sizeof(T) == 8) ? 16 : 32;
+    constexpr int NP = NC / 2;
+    constexpr int EPT = (NC * NC + 255) / 256;  // Gram entries per thread
+    __shared__ cx<T> G[NC][NC + 1];
+    __shared__ cx<T> J[NC][NC + 1];
+    __shared__ cx<T> S[RC][NC + 1];
+    __shared__ T rc_[NP], rs_[NP], rtg_[NP], ra_[NP], rb_[NP];
+    __shared__ cx<T> re_[NP];
+    __shared__ int rp_[NP], rq_[NP], rdo_[NP];
+    __shared__ int cols[NC];
+    __shared__ int nrot_sh;
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    int nc;
+    if (single) {
+        nc = n;
+        for (int c = tid; c < n; c += nth) cols[c] = c;
+    } else {
+        const int a = rr_player(blockIdx.x, rnd, nb), b = rr_player(nb - 1 - blockIdx.x, rnd, nb);
+        const int a0 = a * w, a1 = min(a0 + w, n), b0 = b * w, b1 = min(b0 + w, n);
+        const int na = max(0, a1 - a0), nbb = max(0, b1 - b0);
+        nc = na + nbb;
+        for (int c = tid; c < na; c += nth) cols[c] = a0 + c;
+        for (int c = tid; c < nbb; c += nth) cols[na + c] = b0 + c;
+    }
+    __syncthreads();
+    if (nc < 2) {
+        if (single && tid == 0) {
+            sweeps_out[0] = 1;
+            sweeps_out[1] = 1;
+        }
+        return;
+    }
+    const int nce = nc + (nc & 1);
+    const int npairs = nce / 2;
+    int outer = 0;
+    int converged = 0;
+    for (; outer < max_outer; ++outer) {
+        // ---- Gram matrix of the owned columns ----
+        cx<T> gacc[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) gacc[u] = zero_cx<T>();
+        for (int r0 = 0; r0 < m; r0 += RC) {
+            const int rows = min(RC, m - r0);
+            for (int e = tid; e < rows * nc; e += nth) {
+                const int c = e / rows, rr = e % rows;
+                S[rr][c] = W[(size_t)cols[c] * m + r0 + rr];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int e = tid + u * 256;
+                if (e < nc * nc) {
+                    const int p = e / nc, q = e % nc;
+                    cx<T> acc = gacc[u];
+                    for (int rr = 0; rr < rows; ++rr) cmacc(acc, S[rr][p], S[rr][q]);
+                    gacc[u] = acc;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + u * 256;
+            if (e < nc * nc) {
+                const int p = e / nc, q = e % nc;
+                G[p][q] = gacc[u];
+                J[p][q] = mk<T>(p == q ? T(1) : T(0), T(0));
+            }
+        }
+        __syncthreads();
+
+        // ---- two-sided Jacobi on G, accumulated in J ----
+        int first = 0;
+        for (int isw = 0; isw < inner_max; ++isw) {
+            if (tid == 0) nrot_sh = 0;
+            __syncthreads();
+            for (int step = 0; step < nce - 1; ++step) {
+                if (tid < npairs) {
+                    int p = rr_player(tid, step, nce), q = rr_player(nce - 1 - tid, step, nce);
+                    if (p > q) {
+                        int t = p;
+                        p = q;
+                        q = t;
+                    }
+                    int dd = 0;
+                    if (q < nc) {
+                        const T al = G[p][p].x, be = G[q][q].x;
+                        const cx<T> ga = G[p][q];
+                        const T g = sqrt(norm2(ga));
+                        if (g > T(0) && g > tol * sqrt(al * be)) {
+                            const T zeta = (be - al) / (T(2) * g);
+                            const T t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + hypot(T(1), zeta));
+                            const T c = T(1) / sqrt(T(1) + t * t);
+                            rc_[tid] = c;
+                            rs_[tid] = c * t;
+                            re_[tid] = (T(1) / g) * conj(ga);
+                            rtg_[tid] = t * g;
+                            ra_[tid] = al;
+                            rb_[tid] = be;
+                            dd = 1;
+                            atomicAdd(&nrot_sh, 1);
+                        }
+                    }
+                    rp_[tid] = p;
+                    rq_[tid] = q;
+                    rdo_[tid] = dd;
+                }
+                __syncthreads();
+                // columns: G <- G M, J <- J M, M = [[c, s], [-s e, c e]]
+                for (int e = tid; e < npairs * nc; e += nth) {
+                    const int pi = e / nc, row = e % nc;
+                    if (rdo_[pi]) {
+                        const int p = rp_[pi], q = rq_[pi];
+                        const T c = rc_[pi], s = rs_[pi];
+                        const cx<T> ee = re_[pi];
+                        cx<T> gp = G[row][p], gq = ee * G[row][q];
+                        G[row][p] = c * gp - s * gq;
+                        G[row][q] = s * gp + c * gq;
+                        cx<T> jp = J[row][p], jq = ee * J[row][q];
+                        J[row][p] = c * jp - s * jq;
+                        J[row][q] = s * jp + c * jq;
+                    }
+                }
+                __syncthreads();
+                // rows: G <- M^H G
+                for (int e = tid; e < npairs * nc; e += nth) {
+                    const int pi = e / nc, col = e % nc;
+                    if (rdo_[pi]) {
+                        const int p = rp_[pi], q = rq_[pi];
+                        const T c = rc_[pi], s = rs_[pi];
+                        const cx<T> ec = conj(re_[pi]);
+                        cx<T> gp = G[p][col], gq = ec * G[q][col];
+                        G[p][col] = c * gp - s * gq;
+                        G[q][col] = s * gp + c * gq;
+                    }
+                }
+                __syncthreads();
+                if (tid < npairs && rdo_[tid]) {
+                    const int p = rp_[tid], q = rq_[tid];
+                    G[p][q] = zero_cx<T>();
+                    G[q][p] = zero_cx<T>();
+                    G[p][p] = mk<T>(ra_[tid] - rtg_[tid], T(0));
+                    G[q][q] = mk<T>(rb_[tid] + rtg_[tid], T(0));
+                }
+                __syncthreads();
+            }
+            const int nr = nrot_sh;
+            __syncthreads();
+            if (isw == 0) first = nr;
+            if (nr == 0) break;
+        }
+        if (!single && tid == 0 && first > 0) atomicAdd(rot_counter, first);
+        if (first == 0) {
+            converged = 1;
+            break;
+        }
+
+        // ---- apply J to the owned columns of W and V ----
+        for (int pass = 0; pass < 2; ++pass) {
+            cx<T> *X = pass == 0 ? W : V;
+            const int M = pass == 0 ? m : n;
+            for (int r0 = 0; r0 < M; r0 += RC) {
+                const int rows = min(RC, M - r0);
+                for (int e = tid; e < rows * nc; e += nth) {
+                    const int c = e / rows, rr = e % rows;
+                    S[rr][c] = X[(size_t)cols[c] * M + r0 + rr];
+                }
+                __syncthreads();
+                for (int e = tid; e < rows * nc; e += nth) {
+                    const int q = e / rows, rr = e % rows;
+                    cx<T> acc = zero_cx<T>();
+                    for (int c = 0; c < nc; ++c) cmac(acc, S[rr][c], J[c][q]);
+                    X[(size_t)cols[q] * M + r0 + rr] = acc;
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (single && tid == 0) {
+        sweeps_out[0] = converged ? outer + 1 : outer;
+        sweeps_out[1] = converged;
+    }
+}
+
+template <typename T>
+void launch_jacobi_single(void *W, int m, void *V, int n, double tol, int inner_max,
+                          int max_sweeps, int *sweeps_dev, hipStream_t s) {
+    k_jacobi_block<T, 64><<<1, 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, n, 1, 0, (T)tol,
+                                            inner_max, 1, max_sweeps, nullptr, sweeps_dev);
+}
+
+template <typename T>
+void launch_jacobi_round(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
+                         int inner_max, int ncmax, int *rot_counter, hipStream_t s) {
+    const int grid = nb / 2;
+    if (ncmax <= 16)
+        k_jacobi_block<T, 16><<<grid, 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb, rnd,
+                                                   (T)tol, inner_max, 0, 1, rot_counter, nullptr);
+    else if (ncmax <= 32)
+        k_jacobi_block<T, 32><<<grid, 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb, rnd,
+                                                   (T)tol, inner_max, 0, 1, rot_counter, nullptr);
+    else
+        k_jacobi_block<T, 64><<<grid, 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb, rnd,
+                                                   (T)tol, inner_max, 0, 1, rot_counter, nullptr);
+}
+
+template void launch_jacobi_single<float>(void *, int, void *, int, double, int, int, int *,
+                                          hipStream_t);
+template void launch_jacobi_single<double>(void *, int, void *, int, double, int, int, int *,
+                                           hipStream_t);
+template void launch_jacobi_round<float>(void *, int, void *, int, int, int, int, double, int,
+                                         int, int *, hipStream_t);
+template void launch_jacobi_round<double>(void *, int, void *, int, int, int, int, double, int,
+                                          int, int *, hipStream_t);

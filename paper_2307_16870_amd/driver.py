@@ -1,0 +1,101 @@
+"""Object wrapper over the C ABI handle and a circuit walker.
+
+``EAState`` owns one ``ea_mps`` handle.  ``run`` hands a circuit to the
+library layer by layer (one-qubit operators one by one, then all two-qubit
+operators of the layer in one ``mps_apply_layer`` call); it does no
+arithmetic of its own.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _binding as B
+
+
+class EAState:
+    def __init__(self, n_sites, kind="pure", prec="c128", chi_max=0, local=None, stream=None):
+        self.n = int(n_sites)
+        self.kind = kind
+        self.d = 2 if kind == "pure" else 4
+        k = B.EA_PURE if kind == "pure" else B.EA_MIXED
+        p = {"c128": B.EA_C128, "c64": B.EA_C64, "bf16x3": B.EA_C64_BF16X3}[prec]
+        self.h = B.mps_init_product(self.n, k, p, chi_max, local, stream)
+        self.warnings = 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            B.mps_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---------------------------------------------------------------- calls
+    def set_option(self, opt, val):
+        return B.mps_set_option(self.h, opt, val)
+
+    def set_schedule(self, f_min, n_total, strategy=B.EA_GLOBAL):
+        return B.mps_set_schedule(self.h, f_min, n_total, strategy)
+
+    def apply_1q(self, site, op):
+        return B.mps_apply_1q(self.h, site, op)
+
+    def apply_2q(self, site, op, budget=-1.0):
+        return B.mps_apply_2q(self.h, site, op, budget)
+
+    def apply_layer(self, sites, ops, budgets=None):
+        return B.mps_apply_layer(self.h, sites, ops, budgets)
+
+    def fidelity_estimate(self):
+        return B.mps_fidelity_estimate(self.h)
+
+    def expect(self, sites, widths, ops):
+        return B.mps_expect(self.h, sites, widths, ops)
+
+    def statevector(self):
+        return B.mps_to_statevector(self.h, 2 ** self.n)
+
+    def density(self):
+        dim = 2 ** self.n
+        return B.mps_to_statevector(self.h, dim * dim).reshape(dim, dim)
+
+    def bond_dims(self):
+        return B.mps_bond_dims(self.h, self.n)
+
+    def center(self):
+        return B.mps_center(self.h)
+
+    def gate_log(self):
+        return B.mps_gate_log(self.h)
+
+    def load(self, tensors, center):
+        return B.mps_load(self.h, tensors, center)
+
+    def site(self, i):
+        return B.mps_get_site(self.h, i)
+
+    # -------------------------------------------------------------- circuit
+    def run(self, program, f_min=1.0, strategy=B.EA_GLOBAL, schedule=True):
+        """Apply a ``circuits.Program``; returns the number of warnings."""
+        if schedule:
+            self.set_schedule(f_min, max(1, program.n_2q), strategy)
+        for layer in program.layers:
+            for op in layer:
+                if op.width == 1:
+                    self.apply_1q(op.site, op.mat)
+            twos = [op for op in layer if op.width == 2]
+            if twos:
+                rc, _ = self.apply_layer([op.site for op in twos],
+                                         np.stack([op.mat for op in twos]))
+                if rc > 0:
+                    self.warnings += 1
+        return self.warnings

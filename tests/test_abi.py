@@ -1,0 +1,56 @@
+"""CPU-side checks of the C ABI: the library loads and exports every function
+the header declares (no compute calls, no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ea_mps.h")
+LIB = os.path.join(ROOT, "paper_2307_16870_amd", "_lib", "libeamps.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("mps_", "ea_"))))
+
+
+def test_header_parses():
+    names = declared_functions()
+    for must in ["mps_init_product", "mps_apply_1q", "mps_apply_2q", "mps_apply_layer",
+                 "mps_fidelity_estimate", "mps_expect", "mps_to_statevector"]:
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_names_match_header():
+    import paper_2307_16870_amd as P
+    assert sorted(P.SYMBOLS) == declared_functions()
+    for name in P.SYMBOLS:
+        assert callable(getattr(P, name))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_null_handle_and_last_error():
+    """Argument validation happens on the host before any HIP call."""
+    import paper_2307_16870_amd as P
+    lib = P._binding._lib
+    assert lib.mps_set_schedule(None, 0.9, 10, 1) == P.EA_EINVAL
+    assert "null" in P.ea_last_error()
+    assert lib.mps_fidelity_estimate(None, None, None) == P.EA_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.mps_init_product(1, 0, 0, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(4, 7, 0, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(4, 0, 9, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(4, 0, 0, -1, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    lib.mps_free(None)
