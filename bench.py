@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the entanglement-aware two-site gate update on one MI355X.
+
+Workload (one "step"): the noiseless 1D brickwork circuit of 50 qubits and
+depth 20 with seeded Haar-random U(4) gates, started from |0...0>, run with
+the global target schedule for F_min = 0.99 and a bond cap of 1024 -- 490
+two-site updates (contract, gate, SVD, truncate, fidelity product), plus the
+orthogonality-centre moves between them.  Default arithmetic: complex FP32
+contraction and Jacobi rotations, FP64 singular-value sums, kept-rank search
+and fidelity product.
+
+Prints one JSON line.  ``value`` is two-site updates per second over the
+timed steps (inputs are generated on the host before timing; the state lives
+in device memory throughout).  ``roofline`` reports the kernel family with
+the largest device time, timed with HIP events around each of its launches on
+the library's stream during the timed steps.  ``cpu_baseline`` times the
+CPU oracle on the first layers of the same circuit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "f32_vector_TF": 157.3, "f64_vector_TF": 78.6,
+    "f32_mfma_TF": 157.3, "f64_mfma_TF": 78.6, "bf16_mfma_TF": 2500.0,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_circuit(st, prog, f_min, progress=False):
+    st.reset()
+    st.set_schedule(f_min, prog.n_2q)
+    t0 = time.perf_counter()
+    for li, layer in enumerate(prog.layers):
+        st.run_layer(layer)
+        if progress:
+            log(f"  layer {li} done at {time.perf_counter() - t0:.1f}s")
+
+
+def cpu_baseline(prog, f_min, chi_max, n_layers, budget_s):
+    import numpy as np  # noqa: F401
+    from oracle.mps import OracleMPS
+    o = OracleMPS(prog.n_sites, "pure", chi_max=chi_max)
+    o.set_schedule(f_min, prog.n_2q)
+    t0 = time.perf_counter()
+    n_upd = 0
+    used = 0
+    for layer in prog.layers[:n_layers]:
+        o.apply_layer(layer)
+        n_upd += len(layer)
+        used += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": n_upd / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
+        "sample": (f"first {used} of {len(prog.layers)} layers ({n_upd} of {prog.n_2q} updates, "
+                   f"bonds up to {max(o.bond_dims())}) of the same circuit; complex128 oracle "
+                   f"with its own one-sided Jacobi SVD; {dt:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128", "bf16x3"])
+    ap.add_argument("--depth", type=int, default=20)
+    ap.add_argument("--fp64", action="store_true", help="also time one FP64 step for comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-layers", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import circuits as C
+    import paper_2307_16870_amd as P
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    prog, cfg = C.config_program(2, depth=args.depth)
+    f_min, chi_max = cfg["f_min"], cfg["chi_max"]
+
+    st = P.EAState(prog.n_sites, "pure", args.prec, chi_max=chi_max, stream=stream)
+    # load the kernels' code objects before anything is timed (not a step)
+    tiny = C.brickwork_program(prog.n_sites, 2, 99)
+    run_circuit(st, tiny, 1.0)
+    for w in range(args.warmup):
+        log(f"warmup step {w}")
+        run_circuit(st, prog, f_min, progress=True)
+
+    st.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        log(f"timed step {k}")
+        run_circuit(st, prog, f_min, progress=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fams = {name: st.profile_read(i) for i, name in enumerate(P._binding.K_FAMILY_NAMES)}
+    st.profile(False)
+
+    F, lnF = st.fidelity_estimate()
+    glog = st.gate_log()
+    n_upd = prog.n_2q * args.steps
+    ms_step = 1000.0 * elapsed / args.steps
+    log(f"elapsed {elapsed:.2f}s  P={F:.5f}")
+
+    # dominant kernel family and its roofline
+    dom = max(fams, key=lambda k: fams[k]["ms"])
+    fd = fams[dom]
+    avg_ms = fd["ms"] / max(1, fd["launches"])
+    f64 = args.prec == "c128"
+    peak = PEAKS["f64_vector_TF"] if f64 else PEAKS["f32_vector_TF"]
+    achieved = fd["flops"] / (fd["ms"] * 1e-3) / 1e12 if fd["ms"] > 0 else 0.0
+    roofline = {
+        "kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": None,
+        "avg_launch_ms": avg_ms, "launches": fd["launches"],
+        "algorithmic_flops_per_launch": fd["flops"] / max(1, fd["launches"]),
+        "algorithmic_bytes_per_launch": fd["bytes"] / max(1, fd["launches"]),
+        "achieved_GBs_algorithmic": fd["bytes"] / (fd["ms"] * 1e-3) / 1e9 if fd["ms"] > 0 else 0.0,
+    }
+
+    out = {
+        "metric": "2-site gate updates/s & circuit time at F>=0.99, mixed-prec vs FP64, 1 GPU",
+        "value": n_upd / elapsed,
+        "unit": "updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if f64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"brickwork-haar-50q-depth{args.depth}-Fmin0.99-chi1024",
+                   "n_qubits": prog.n_sites, "depth": args.depth, "updates_per_step": prog.n_2q,
+                   "f_min": f_min, "chi_max": chi_max, "schedule": "global", "prec": args.prec},
+        "circuit_time_s": ms_step / 1000.0,
+        "final_fidelity_estimate": F,
+        "capped_updates": int(sum(r["capped"] for r in glog)),
+        "max_bond": int(max(st.bond_dims())),
+        "kernels_ms": {k: round(v["ms"], 3) for k, v in fams.items()},
+        "roofline": roofline,
+    }
+    if args.fp64 and args.prec != "c128":
+        log("fp64 comparison step")
+        st64 = P.EAState(prog.n_sites, "pure", "c128", chi_max=chi_max, stream=stream)
+        run_circuit(st64, tiny, 1.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_circuit(st64, prog, f_min, progress=True)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        F64, _ = st64.fidelity_estimate()
+        out["fp64"] = {"ms_per_step": 1000 * t64, "updates_per_s": prog.n_2q / t64,
+                       "final_fidelity_estimate": F64,
+                       "speedup_mixed_vs_fp64": t64 / (ms_step / 1000.0)}
+        st64.close()
+    st.close()
+    if not args.no_cpu:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(prog, f_min, chi_max, args.cpu_layers, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,7 +83,10 @@ enum ea_option {
     EA_OPT_MAX_SWEEPS = 1,   /* default 40 */
     EA_OPT_TAU = 2,          /* numerical-zero cutoff tau*s_0; 1e-13 (FP64), 2e-6 (FP32) */
     EA_OPT_BLOCK = 3,        /* Jacobi column-block width (0 = automatic) */
-    EA_OPT_CHI_MAX = 4       /* cap on kept rank; 0 = none */
+    EA_OPT_CHI_MAX = 4,      /* cap on kept rank; 0 = none */
+    EA_OPT_INNER_SWEEPS = 5, /* rotation sweeps over a block pair's Gram per round (default 2) */
+    EA_OPT_JACOBI_KERNEL = 6 /* 0: Gram / rotations / apply as three kernels (MFMA);
+                                1: one fused kernel per round (vector ALU) */
 };
 
 /* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */
@@ -187,6 +190,36 @@ int mps_load(ea_mps *h, const int *bond_dims, const double *data, int center);
 /* Copy site tensor `site` (chi_l*d*chi_r complex) into out; dims receives
  * (chi_l, d, chi_r).  EA_ETOOBIG if out_complex_len is too small. */
 int mps_get_site(ea_mps *h, int site, double *out, size_t out_complex_len, int *dims);
+
+/* Reset the handle to a product state exactly as mps_init_product would
+ * create it (local as there), keeping its device buffers.  Clears the
+ * fidelity estimate, the gate counter, the schedule and the gate log. */
+int mps_reset_product(ea_mps *h, const double *local);
+
+/* Kernel families timed by mps_profile (tracing aid, Sec. VI bookkeeping is
+ * unaffected). */
+enum ea_kfamily {
+    EA_K_THETA = 0,        /* two-site contraction + gate */
+    EA_K_JACOBI_ROUND = 1, /* one round of the multi-workgroup block Jacobi */
+    EA_K_JACOBI_SMALL = 2, /* single-workgroup Jacobi (<= 64 columns) */
+    EA_K_NORMS = 3,        /* singular values as column norms */
+    EA_K_TRUNC = 4,        /* sort + kept-rank search */
+    EA_K_GATHER = 5,       /* write-back of the new site tensors */
+    EA_K_GEMM = 6,         /* absorb products (centre moves, chain contraction) */
+    EA_K_OTHER = 7,
+    EA_K_COUNT = 8
+};
+
+/* enable = 1: start timing every kernel launch of this handle with a pair of
+ * HIP events on its stream (counters reset); 0: stop.  Adds a small
+ * per-launch overhead. */
+int mps_profile(ea_mps *h, int enable);
+
+/* Accumulated device time (ms), number of launches, and the algorithmic
+ * floating-point operations and bytes of those launches for one family.
+ * Synchronises the handle's stream.  Any output pointer may be NULL. */
+int mps_profile_read(ea_mps *h, int family, double *ms_total, long *launches,
+                     double *flops, double *bytes);
 
 /* Message for the last non-zero status returned on this thread. */
 const char *ea_last_error(void);

@@ -21,13 +21,19 @@ EA_OK, EA_WARN_CAPPED, EA_WARN_NOCONV = 0, 1, 2
 EA_EINVAL, EA_ERANGE, EA_ENOMEM, EA_EHIP, EA_ETOOBIG = -1, -2, -3, -4, -5
 EA_NAIVE, EA_GLOBAL, EA_NEAREST = 0, 1, 2
 EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
+EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL = 5, 6
 
 SYMBOLS = [
     "mps_init_product", "mps_free", "mps_set_option", "mps_set_schedule", "mps_apply_1q",
     "mps_apply_2q", "mps_apply_layer", "mps_fidelity_estimate", "mps_expect",
     "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
-    "mps_get_site", "ea_last_error",
+    "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read", "ea_last_error",
 ]
+
+EA_K_THETA, EA_K_JACOBI_ROUND, EA_K_JACOBI_SMALL, EA_K_NORMS = 0, 1, 2, 3
+EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_COUNT = 4, 5, 6, 7, 8
+K_FAMILY_NAMES = ["theta", "jacobi_round", "jacobi_small", "norms", "trunc", "gather", "gemm",
+                  "other"]
 
 
 class EAError(RuntimeError):
@@ -66,6 +72,9 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_gate_log": (I, [P, ct.POINTER(GateRecord), S, ct.POINTER(S)]),
         "mps_load": (I, [P, ip, dp, I]),
         "mps_get_site": (I, [P, I, dp, S, ip]),
+        "mps_reset_product": (I, [P, dp]),
+        "mps_profile": (I, [P, I]),
+        "mps_profile_read": (I, [P, I, dp, ct.POINTER(ct.c_long), dp, dp]),
         "ea_last_error": (ct.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -210,3 +219,20 @@ def mps_get_site(h, site):
     out = np.zeros(int(np.prod(dims)), dtype=np.complex128)
     _chk(_lib.mps_get_site(h, int(site), _dp(out), out.size, _ip(dims)))
     return out.reshape(tuple(int(x) for x in dims))
+
+
+def mps_reset_product(h, local=None):
+    loc = None if local is None else _c(local)
+    return _chk(_lib.mps_reset_product(h, _dp(loc) if loc is not None else None))
+
+
+def mps_profile(h, enable):
+    return _chk(_lib.mps_profile(h, int(bool(enable))))
+
+
+def mps_profile_read(h, family):
+    """Returns dict(ms, launches, flops, bytes) for one kernel family."""
+    ms, n, fl, by = ct.c_double(), ct.c_long(), ct.c_double(), ct.c_double()
+    _chk(_lib.mps_profile_read(h, int(family), ct.byref(ms), ct.byref(n), ct.byref(fl),
+                               ct.byref(by)))
+    return {"ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value}

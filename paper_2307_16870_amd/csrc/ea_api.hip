@@ -51,6 +51,8 @@ struct ea_mps {
     long n_total = 1;
     int strategy = EA_GLOBAL;
     // workspace
+    DevBuf jpart, jmat, jflag;
+    int inner_round = 2, jkernel = 0;
     DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
     ea_dev_rec *rec_host = nullptr;
     int *int_host = nullptr;
@@ -66,6 +68,17 @@ struct ea_mps {
     int inner_max = 12;
     std::vector<ea_gate_record> log;
     bool poisoned = false;
+    // per-launch event timing (mps_profile)
+    struct ProfRec {
+        hipEvent_t a, b;
+        int fam;
+        double flops, bytes;
+    };
+    bool prof_on = false;
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    double prof_ms[EA_K_COUNT] = {0}, prof_flops[EA_K_COUNT] = {0}, prof_bytes[EA_K_COUNT] = {0};
+    long prof_cnt[EA_K_COUNT] = {0};
 };
 
 namespace {
@@ -86,6 +99,51 @@ namespace {
         int rc_ = (x);             \
         if (rc_ < 0) return rc_;   \
     } while (0)
+
+hipEvent_t ev_get(ea_mps *h) {
+    if (!h->prof_pool.empty()) {
+        hipEvent_t e = h->prof_pool.back();
+        h->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Times the launches enqueued during its lifetime with an event pair.
+struct ProfScope {
+    ea_mps *h;
+    hipEvent_t a = nullptr;
+    int fam;
+    double fl, by;
+    ProfScope(ea_mps *h_, int fam_, double fl_, double by_) : h(h_), fam(fam_), fl(fl_), by(by_) {
+        if (h->prof_on && (a = ev_get(h)) != nullptr) (void)hipEventRecord(a, h->stream);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = ev_get(h);
+        if (!b) return;
+        (void)hipEventRecord(b, h->stream);
+        h->prof_pending.push_back({a, b, fam, fl, by});
+    }
+};
+
+// Accumulate completed event pairs (call after a stream synchronisation).
+void prof_harvest(ea_mps *h) {
+    for (auto &r : h->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            h->prof_ms[r.fam] += ms;
+            h->prof_cnt[r.fam] += 1;
+            h->prof_flops[r.fam] += r.flops;
+            h->prof_bytes[r.fam] += r.bytes;
+        }
+        h->prof_pool.push_back(r.a);
+        h->prof_pool.push_back(r.b);
+    }
+    h->prof_pending.clear();
+}
 
 int ensure(ea_mps *h, DevBuf &b, size_t bytes) {
     if (bytes <= b.bytes) return EA_OK;
@@ -182,24 +240,53 @@ int svd_core(ea_mps *h, int m, int n) {
     int *sweeps_dev = (int *)h->ints.p;
     int *counter = sweeps_dev + 2;
     const double tol = h->tol > 0 ? h->tol : default_tol<T>(m);
-    launch_eye<T>(h->V.p, n, h->stream);
+    const double c = (double)h->csz;
+    {
+        ProfScope ps(h, EA_K_OTHER, 0.0, c * n * (double)n);
+        launch_eye<T>(h->V.p, n, h->stream);
+    }
     if (n <= 64) {
+        ProfScope ps(h, EA_K_JACOBI_SMALL, 0.0, 2.0 * c * (m + n) * (double)n);
         launch_jacobi_single<T>(h->W.p, m, h->V.p, n, tol, h->inner_max, h->max_sweeps,
                                 sweeps_dev, h->stream);
         LAUNCHCHK(h);
         return EA_OK;
     }
-    int w = h->block > 0 ? h->block : (n <= 256 ? 8 : 16);
+    const bool three = h->jkernel == 0;
+    int w = h->block > 0 ? h->block : (three ? (n <= 256 ? 16 : 32) : (n <= 256 ? 8 : 16));
     if (2 * w > 64) w = 32;
     const int ncmax = 2 * w <= 16 ? 16 : (2 * w <= 32 ? 32 : 64);
     int nb = (n + w - 1) / w;
     nb += nb & 1;
+    if (three) {
+        TRY(ensure(h, h->jpart, h->csz * jacobi_round3_partial_elems(m, n, w)));
+        TRY(ensure(h, h->jmat, h->csz * jacobi_round3_j_elems(n, w)));
+        TRY(ensure(h, h->jflag, sizeof(int) * (nb / 2 + 1)));
+    }
     int sweeps = 0, conv = 0;
     for (int sw = 0; sw < h->max_sweeps; ++sw) {
         launch_fill_int(counter, 1, 0, h->stream);
-        for (int rnd = 0; rnd < nb - 1; ++rnd)
-            launch_jacobi_round<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, 6, ncmax, counter,
-                                   h->stream);
+        for (int rnd = 0; rnd < nb - 1; ++rnd) {
+            // algorithmic work of one round: every column pair block forms its
+            // Hermitian Gram (4 m nc^2 flops) and rotates nc columns of W and V
+            // (8 (m + n) nc^2 flops); W and V are read and written once
+            double fl = 0.0;
+            for (int p = 0; p < nb / 2; ++p) {
+                const int a = p == 0 ? 0 : (p - 1 + rnd) % (nb - 1) + 1;
+                const int bq = nb - 1 - p;
+                const int b = bq == 0 ? 0 : (bq - 1 + rnd) % (nb - 1) + 1;
+                const int nc = std::max(0, std::min(w, n - a * w)) + std::max(0, std::min(w, n - b * w));
+                fl += (4.0 * m + 8.0 * (m + n)) * nc * (double)nc;
+            }
+            ProfScope ps(h, EA_K_JACOBI_ROUND, fl, 2.0 * c * (m + n) * (double)n);
+            if (three)
+                launch_jacobi_round3<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
+                                        h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                        h->stream);
+            else
+                launch_jacobi_round<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, 6, ncmax, counter,
+                                       h->stream);
+        }
         LAUNCHCHK(h);
         HIPCHK(h, hipMemcpyAsync(h->int_host, counter, sizeof(int), hipMemcpyDeviceToHost,
                                  h->stream));
@@ -223,20 +310,28 @@ int factor_and_decide(ea_mps *h, int mw, int nw, double f_t, int mode, int force
     TRY(ensure(h, h->s_sorted, sizeof(double) * nw));
     TRY(ensure(h, h->perm, sizeof(int) * nw));
     TRY(svd_core<T>(h, mw, nw));
-    launch_colnorms<T>(h->W.p, mw, nw, (double *)h->s_raw.p, h->stream);
-    launch_sort_trunc((const double *)h->s_raw.p, nw, f_t, h->chi_max, h->tau, mode, forced_k,
-                      (const int *)h->ints.p, (int *)h->perm.p, (double *)h->s_sorted.p,
-                      (ea_dev_rec *)h->rec.p, h->stream);
+    {
+        ProfScope ps(h, EA_K_NORMS, 4.0 * mw * (double)nw, (double)h->csz * mw * (double)nw);
+        launch_colnorms<T>(h->W.p, mw, nw, (double *)h->s_raw.p, h->stream);
+    }
+    {
+        ProfScope ps(h, EA_K_TRUNC, (double)nw, 24.0 * nw);
+        launch_sort_trunc((const double *)h->s_raw.p, nw, f_t, h->chi_max, h->tau, mode,
+                          forced_k, (const int *)h->ints.p, (int *)h->perm.p,
+                          (double *)h->s_sorted.p, (ea_dev_rec *)h->rec.p, h->stream);
+    }
     LAUNCHCHK(h);
     HIPCHK(h, hipMemcpyAsync(h->rec_host, h->rec.p, sizeof(ea_dev_rec), hipMemcpyDeviceToHost,
                              h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    prof_harvest(h);
     return EA_OK;
 }
 
 template <typename T>
 void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int es, int ec,
             int transposed, void *out) {
+    ProfScope ps(h, EA_K_GATHER, 0.0, 2.0 * (double)h->csz * k * (double)X);
     launch_gather<T>(src, ld, (const int *)h->perm.p, (const double *)h->s_sorted.p,
                      (const ea_dev_rec *)h->rec.p, k, X, conj_src, es, ec, transposed, out,
                      h->stream);
@@ -252,7 +347,10 @@ int move_right(ea_mps *h) {
     if (nw > EA_SORT_MAX) return set_err(EA_ETOOBIG, "bond too large for centre move");
     TRY(ensure(h, h->W, h->csz * (size_t)mw * nw));
     TRY(ensure(h, h->V, h->csz * (size_t)nw * nw));
-    launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, orient, h->stream);
+    {
+        ProfScope ps(h, EA_K_OTHER, 0.0, 2.0 * (double)h->csz * M * (double)N);
+        launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, orient, h->stream);
+    }
     TRY(factor_and_decide<T>(h, mw, nw, 1.0, 1, 0));
     const int k = h->rec_host->k;
     if (!(h->rec_host->s0 > 0.0)) return set_err(EA_EINVAL, "zero site tensor");
@@ -267,8 +365,12 @@ int move_right(ea_mps *h) {
         gather<T>(h, h->W.p, N, k, N, 1, 0, 0, 0, h->X.p);
     }
     TRY(ensure(h, h->spare, h->csz * (size_t)k * d * chi2));
-    launch_gemm<T>(h->X.p, h->site[c + 1].p, h->spare.p, k, d * chi2, N, N, d * chi2, d * chi2,
-                   h->stream);
+    {
+        ProfScope ps(h, EA_K_GEMM, 8.0 * k * (double)(d * chi2) * N,
+                     (double)h->csz * ((double)k * N + (double)N * d * chi2 + (double)k * d * chi2));
+        launch_gemm<T>(h->X.p, h->site[c + 1].p, h->spare.p, k, d * chi2, N, N, d * chi2,
+                       d * chi2, h->stream);
+    }
     LAUNCHCHK(h);
     std::swap(h->site[c + 1], h->spare);
     h->bond[c + 1] = k;
@@ -286,7 +388,10 @@ int move_left(ea_mps *h) {
     if (nw > EA_SORT_MAX) return set_err(EA_ETOOBIG, "bond too large for centre move");
     TRY(ensure(h, h->W, h->csz * (size_t)mw * nw));
     TRY(ensure(h, h->V, h->csz * (size_t)nw * nw));
-    launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, orient, h->stream);
+    {
+        ProfScope ps(h, EA_K_OTHER, 0.0, 2.0 * (double)h->csz * M * (double)N);
+        launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, orient, h->stream);
+    }
     TRY(factor_and_decide<T>(h, mw, nw, 1.0, 1, 0));
     const int k = h->rec_host->k;
     if (!(h->rec_host->s0 > 0.0)) return set_err(EA_EINVAL, "zero site tensor");
@@ -301,7 +406,11 @@ int move_left(ea_mps *h) {
         gather<T>(h, h->V.p, M, k, M, 0, 1, 0, 1, h->X.p);
     }
     TRY(ensure(h, h->spare, h->csz * (size_t)rowsP * k));
-    launch_gemm<T>(h->site[c - 1].p, h->X.p, h->spare.p, rowsP, k, M, M, k, k, h->stream);
+    {
+        ProfScope ps(h, EA_K_GEMM, 8.0 * rowsP * (double)k * M,
+                     (double)h->csz * ((double)rowsP * M + (double)M * k + (double)rowsP * k));
+        launch_gemm<T>(h->site[c - 1].p, h->X.p, h->spare.p, rowsP, k, M, M, k, k, h->stream);
+    }
     LAUNCHCHK(h);
     std::swap(h->site[c - 1], h->spare);
     h->bond[c] = k;
@@ -332,8 +441,15 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
     TRY(ensure(h, h->V, h->csz * (size_t)nw * nw));
     void *G = nullptr;
     TRY(stage<T>(h, op, (size_t)d * d * d * d, &G));
-    launch_theta<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d, orient,
-                    h->stream);
+    {
+        const double dd = d;
+        ProfScope ps(h, EA_K_THETA,
+                     8.0 * dd * dd * chiL * (double)chiM * chiR + 8.0 * dd * dd * dd * dd * chiL * (double)chiR,
+                     (double)h->csz * (dd * chiL * chiM + dd * chiM * (double)chiR +
+                                       dd * dd * chiL * (double)chiR + dd * dd * dd * dd));
+        launch_theta<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d, orient,
+                        h->stream);
+    }
     LAUNCHCHK(h);
     TRY(factor_and_decide<T>(h, mw, nw, f_t, 0, forced_k));
     const ea_dev_rec rec = *h->rec_host;
@@ -709,8 +825,10 @@ void mps_free(ea_mps *h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
+    prof_harvest(h);
+    for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     for (auto &b : h->site) free_buf(b);
-    DevBuf *bufs[] = {&h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
+    DevBuf *bufs[] = {&h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
                       &h->stage_dev};
     for (DevBuf *b : bufs) free_buf(*b);
@@ -743,6 +861,14 @@ int mps_set_option(ea_mps *h, int option, double value) {
     case EA_OPT_CHI_MAX:
         if (!(value >= 0) || value > 1e9) return set_err(EA_EINVAL, "chi_max out of range");
         h->chi_max = (int)value;
+        return EA_OK;
+    case EA_OPT_INNER_SWEEPS:
+        if (!(value >= 1) || value > 50) return set_err(EA_EINVAL, "inner sweeps out of range");
+        h->inner_round = (int)value;
+        return EA_OK;
+    case EA_OPT_JACOBI_KERNEL:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi kernel must be 0 or 1");
+        h->jkernel = (int)value;
         return EA_OK;
     default:
         return set_err(EA_EINVAL, "unknown option %d", option);
@@ -914,6 +1040,54 @@ int mps_get_site(ea_mps *h, int site, double *out, size_t out_complex_len, int *
     if (!out) return EA_OK;
     if (out_complex_len < sz) return set_err(EA_ETOOBIG, "need %zu entries", sz);
     return h->f64 ? get_site_impl<double>(h, site, out) : get_site_impl<float>(h, site, out);
+}
+
+int mps_reset_product(ea_mps *h, const double *local) {
+    TRY(check(h));
+    const int n = h->n, d = h->d;
+    if (local && !finite_cplx(local, (size_t)n * d))
+        return set_err(EA_EINVAL, "local state has non-finite entries");
+    std::vector<double> host(2 * (size_t)n * d, 0.0);
+    if (local)
+        std::memcpy(host.data(), local, host.size() * sizeof(double));
+    else
+        for (int i = 0; i < n; ++i) host[2 * (size_t)i * d] = 1.0;
+    std::vector<int> dims(n + 1, 1);
+    int rc = h->f64 ? load_impl<double>(h, dims.data(), host.data(), 0)
+                    : load_impl<float>(h, dims.data(), host.data(), 0);
+    if (rc < 0) return rc;
+    h->lnP = h->lnS = 0.0;
+    h->g = 0;
+    h->has_sched = false;
+    h->log.clear();
+    return EA_OK;
+}
+
+int mps_profile(ea_mps *h, int enable) {
+    TRY(check(h));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    if (enable) {
+        for (int f = 0; f < EA_K_COUNT; ++f) {
+            h->prof_ms[f] = h->prof_flops[f] = h->prof_bytes[f] = 0.0;
+            h->prof_cnt[f] = 0;
+        }
+    }
+    h->prof_on = enable != 0;
+    return EA_OK;
+}
+
+int mps_profile_read(ea_mps *h, int family, double *ms_total, long *launches, double *flops,
+                     double *bytes) {
+    TRY(check(h));
+    if (family < 0 || family >= EA_K_COUNT) return set_err(EA_EINVAL, "bad kernel family");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    if (ms_total) *ms_total = h->prof_ms[family];
+    if (launches) *launches = h->prof_cnt[family];
+    if (flops) *flops = h->prof_flops[family];
+    if (bytes) *bytes = h->prof_bytes[family];
+    return EA_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,398 @@
+// Multi-workgroup round of the block one-sided Jacobi SVD, split in three
+// kernels so that the two dense contractions of a round run on MFMA over the
+// whole chip and only the small rotation search is per block pair:
+//
+//   k_jgram : partial Gram matrices  G_c = W[rows_c, cols]^H W[rows_c, cols]
+//             (block pair x row chunk workgroups, MFMA 16x16x4)
+//   k_jeig  : G = sum_c G_c, two-sided Jacobi rotations on G accumulated in J
+//             (one workgroup per block pair)
+//   k_japply: W[rows, cols] <- W[rows, cols] J and V[rows, cols] <- V[rows, cols] J
+//             (block pair x row chunk workgroups, MFMA 16x16x4)
+//
+// The rotation of a column pair is the Hestenes one-sided rotation expressed
+// on the Gram matrix (symmetric 2x2 Schur rotation of [[a, |g|], [|g|, b]]
+// after removing the phase of g).  Block pairs follow the round-robin
+// (circle method) ordering of the blocks.  W, V are column-major.
+#include "ea_dev.h"
+#include "ea_kernels.h"
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+// Output layout of one 16x16 tile: lane l, value v holds D[row(l, v)][l % 16]
+// (measured on gfx950: f32 rows 4*(l/16)+v, f64 rows l/16+4v).  Inputs: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+template <>
+struct Mfma<float> {
+    typedef f4v acc;
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
+    static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ acc op(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<double> {
+    typedef d4v acc;
+    static __device__ __forceinline__ int row(int lane, int v) { return lane / 16 + 4 * v; }
+    static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ __forceinline__ acc op(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// Columns owned by block pair `pair` in round `rnd` (blocks of width w).
+__device__ __forceinline__ int pair_columns(int pair, int rnd, int nb, int w, int n, int *cols,
+                                            int tid, int nth) {
+    const int a = rr_player(pair, rnd, nb), b = rr_player(nb - 1 - pair, rnd, nb);
+    const int a0 = a * w, a1 = min(a0 + w, n), b0 = b * w, b1 = min(b0 + w, n);
+    const int na = max(0, a1 - a0), nbb = max(0, b1 - b0);
+    for (int c = tid; c < na; c += nth) cols[c] = a0 + c;
+    for (int c = tid; c < nbb; c += nth) cols[na + c] = b0 + c;
+    return na + nbb;
+}
+
+constexpr int JRS = 64;  // rows staged in LDS per step
+
+// Load rows [r0, r0+JRS) of the owned columns into split real/imag LDS planes,
+// zero-padding rows >= r_end and columns >= nc.
+template <typename T, int NC>
+__device__ __forceinline__ void stage_rows(const cx<T> *__restrict__ X, int M, const int *cols,
+                                           int nc, int r0, int r_end, T (*Sr)[NC + 1],
+                                           T (*Si)[NC + 1], int tid) {
+    for (int e = tid; e < JRS * NC; e += 256) {
+        const int c = e / JRS, rr = e % JRS, row = r0 + rr;
+        cx<T> v = zero_cx<T>();
+        if (c < nc && row < r_end) v = X[(size_t)cols[c] * M + row];
+        Sr[rr][c] = v.x;
+        Si[rr][c] = v.y;
+    }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int m, int n, int w,
+                                               int nb, int rnd, int rpc,
+                                               cx<T> *__restrict__ partial) {
+    using MF = Mfma<T>;
+    constexpr int NT = NC / 16;
+    constexpr int NU = NT * (NT + 1) / 2;  // upper-triangular 16x16 tiles
+    constexpr int UPW = (NU + 3) / 4;       // tiles per wave
+    __shared__ T Sr[JRS][NC + 1], Si[JRS][NC + 1];
+    __shared__ int cols[NC];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int pair = blockIdx.x, chunk = blockIdx.y, nchunks = gridDim.y;
+    const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, 256);
+    const int r_begin = chunk * rpc, r_end = min(m, r_begin + rpc);
+    int ti_[UPW], tj_[UPW];
+#pragma unroll
+    for (int u = 0; u < UPW; ++u) {
+        int t = wave + 4 * u, ti = 0, tj = 0, k = 0;
+        ti_[u] = -1;
+        for (ti = 0; ti < NT; ++ti)
+            for (tj = ti; tj < NT; ++tj, ++k)
+                if (k == t) {
+                    ti_[u] = ti;
+                    tj_[u] = tj;
+                }
+    }
+    typename MF::acc re[UPW], im[UPW];
+#pragma unroll
+    for (int u = 0; u < UPW; ++u) {
+        re[u] = MF::zero();
+        im[u] = MF::zero();
+    }
+    __syncthreads();
+    for (int r0 = r_begin; r0 < r_end; r0 += JRS) {
+        stage_rows<T, NC>(W, m, cols, nc, r0, r_end, Sr, Si, tid);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < UPW; ++u) {
+            if (ti_[u] < 0) continue;
+            const int pc = ti_[u] * 16 + lane % 16, qc = tj_[u] * 16 + lane % 16;
+#pragma unroll 4
+            for (int k0 = 0; k0 < JRS; k0 += 4) {
+                const int kr = k0 + lane / 16;
+                const T ar = Sr[kr][pc], ai = Si[kr][pc];
+                const T br = Sr[kr][qc], bi = Si[kr][qc];
+                re[u] = MF::op(ar, br, re[u]);
+                re[u] = MF::op(ai, bi, re[u]);
+                im[u] = MF::op(ar, bi, im[u]);
+                im[u] = MF::op(-ai, br, im[u]);
+            }
+        }
+        __syncthreads();
+    }
+    cx<T> *out = partial + ((size_t)pair * nchunks + chunk) * NC * NC;
+#pragma unroll
+    for (int u = 0; u < UPW; ++u) {
+        if (ti_[u] < 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = ti_[u] * 16 + MF::row(lane, v), q = tj_[u] * 16 + lane % 16;
+            out[p * NC + q] = mk<T>(re[u][v], im[u][v]);
+        }
+    }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial, int nchunks,
+                                              int n, int w, int nb, int rnd, T tol,
+                                              int inner_max, cx<T> *__restrict__ Jout,
+                                              int *__restrict__ rotflag,
+                                              int *__restrict__ rot_counter) {
+    constexpr int NP = NC / 2;
+    __shared__ cx<T> G[NC][NC + 1];
+    __shared__ cx<T> J[NC][NC + 1];
+    __shared__ T rc_[NP], rs_[NP], rtg_[NP], ra_[NP], rb_[NP];
+    __shared__ cx<T> re_[NP];
+    __shared__ int rp_[NP], rq_[NP], rdo_[NP];
+    __shared__ int cols[NC];
+    __shared__ int nrot_sh;
+    const int tid = threadIdx.x, nth = 256, pair = blockIdx.x;
+    const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, nth);
+    // sum the partial Gram tiles (upper triangle) in a fixed order
+    const cx<T> *src = partial + (size_t)pair * nchunks * NC * NC;
+    for (int e = tid; e < NC * NC; e += nth) {
+        const int p = e / NC, q = e % NC;
+        if (p <= q) {
+            double sx = 0.0, sy = 0.0;
+            for (int c = 0; c < nchunks; ++c) {
+                const cx<T> v = src[(size_t)c * NC * NC + e];
+                sx += (double)v.x;
+                sy += (double)v.y;
+            }
+            G[p][q] = mk<T>((T)sx, (T)sy);
+            if (p != q) G[q][p] = mk<T>((T)sx, (T)-sy);
+            else G[p][p] = mk<T>((T)sx, T(0));
+        }
+        J[p][q] = mk<T>(p == q ? T(1) : T(0), T(0));
+    }
+    __syncthreads();
+    const int nce = nc + (nc & 1);
+    const int npairs = nce / 2;
+    int first = 0;
+    if (nc >= 2) {
+        for (int isw = 0; isw < inner_max; ++isw) {
+            if (tid == 0) nrot_sh = 0;
+            __syncthreads();
+            for (int step = 0; step < nce - 1; ++step) {
+                if (tid < npairs) {
+                    int p = rr_player(tid, step, nce), q = rr_player(nce - 1 - tid, step, nce);
+                    if (p > q) {
+                        const int t = p;
+                        p = q;
+                        q = t;
+                    }
+                    int dd = 0;
+                    if (q < nc) {
+                        const T al = G[p][p].x, be = G[q][q].x;
+                        const cx<T> ga = G[p][q];
+                        const T g = sqrt(norm2(ga));
+                        if (g > T(0) && g > tol * sqrt(al * be)) {
+                            const T zeta = (be - al) / (T(2) * g);
+                            const T t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + hypot(T(1), zeta));
+                            const T c = T(1) / sqrt(T(1) + t * t);
+                            rc_[tid] = c;
+                            rs_[tid] = c * t;
+                            re_[tid] = (T(1) / g) * conj(ga);
+                            rtg_[tid] = t * g;
+                            ra_[tid] = al;
+                            rb_[tid] = be;
+                            dd = 1;
+                            atomicAdd(&nrot_sh, 1);
+                        }
+                    }
+                    rp_[tid] = p;
+                    rq_[tid] = q;
+                    rdo_[tid] = dd;
+                }
+                __syncthreads();
+                for (int e = tid; e < npairs * nc; e += nth) {
+                    const int pi = e / nc, row = e % nc;
+                    if (rdo_[pi]) {
+                        const int p = rp_[pi], q = rq_[pi];
+                        const T c = rc_[pi], s = rs_[pi];
+                        const cx<T> ee = re_[pi];
+                        const cx<T> gp = G[row][p], gq = ee * G[row][q];
+                        G[row][p] = c * gp - s * gq;
+                        G[row][q] = s * gp + c * gq;
+                        const cx<T> jp = J[row][p], jq = ee * J[row][q];
+                        J[row][p] = c * jp - s * jq;
+                        J[row][q] = s * jp + c * jq;
+                    }
+                }
+                __syncthreads();
+                for (int e = tid; e < npairs * nc; e += nth) {
+                    const int pi = e / nc, col = e % nc;
+                    if (rdo_[pi]) {
+                        const int p = rp_[pi], q = rq_[pi];
+                        const T c = rc_[pi], s = rs_[pi];
+                        const cx<T> ec = conj(re_[pi]);
+                        const cx<T> gp = G[p][col], gq = ec * G[q][col];
+                        G[p][col] = c * gp - s * gq;
+                        G[q][col] = s * gp + c * gq;
+                    }
+                }
+                __syncthreads();
+                if (tid < npairs && rdo_[tid]) {
+                    const int p = rp_[tid], q = rq_[tid];
+                    G[p][q] = zero_cx<T>();
+                    G[q][p] = zero_cx<T>();
+                    G[p][p] = mk<T>(ra_[tid] - rtg_[tid], T(0));
+                    G[q][q] = mk<T>(rb_[tid] + rtg_[tid], T(0));
+                }
+                __syncthreads();
+            }
+            const int nr = nrot_sh;
+            __syncthreads();
+            if (isw == 0) first = nr;
+            if (nr == 0) break;
+        }
+    }
+    cx<T> *jo = Jout + (size_t)pair * NC * NC;
+    for (int e = tid; e < NC * NC; e += nth) {
+        const int p = e / NC, q = e % NC;
+        jo[e] = (p < nc && q < nc) ? J[p][q] : zero_cx<T>();
+    }
+    if (tid == 0) {
+        rotflag[pair] = first > 0 ? 1 : 0;
+        if (first > 0) atomicAdd(rot_counter, first);
+    }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx<T> *__restrict__ V,
+                                                int n, int w, int nb, int rnd, int nchW, int rpcW,
+                                                int rpcV, const cx<T> *__restrict__ Jin,
+                                                const int *__restrict__ rotflag) {
+    using MF = Mfma<T>;
+    constexpr int NT = NC / 16;
+    constexpr int TPW = (4 * NT) / 4;  // (JRS/16 row tiles x NT col tiles) / 4 waves
+    __shared__ T Sr[JRS][NC + 1], Si[JRS][NC + 1];
+    __shared__ T Jr[NC][NC + 1], Ji[NC][NC + 1];
+    __shared__ int cols[NC];
+    const int pair = blockIdx.x;
+    if (!rotflag[pair]) return;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const bool isW = (int)blockIdx.y < nchW;
+    cx<T> *X = isW ? W : V;
+    const int M = isW ? m : n;
+    const int chunk = isW ? blockIdx.y : blockIdx.y - nchW;
+    const int rpc = isW ? rpcW : rpcV;
+    const int r_begin = chunk * rpc, r_end = min(M, r_begin + rpc);
+    if (r_begin >= r_end) return;
+    const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, 256);
+    const cx<T> *jin = Jin + (size_t)pair * NC * NC;
+    for (int e = tid; e < NC * NC; e += 256) {
+        const cx<T> v = jin[e];
+        Jr[e / NC][e % NC] = v.x;
+        Ji[e / NC][e % NC] = v.y;
+    }
+    for (int r0 = r_begin; r0 < r_end; r0 += JRS) {
+        __syncthreads();
+        stage_rows<T, NC>(X, M, cols, nc, r0, r_end, Sr, Si, tid);
+        __syncthreads();
+        typename MF::acc re[TPW], im[TPW];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            re[u] = MF::zero();
+            im[u] = MF::zero();
+            const int t = wave + 4 * u;
+            const int ti = t / NT, tj = t % NT;
+            const int ar_row = ti * 16 + lane % 16, bq = tj * 16 + lane % 16;
+#pragma unroll 4
+            for (int k0 = 0; k0 < NC; k0 += 4) {
+                const int kc = k0 + lane / 16;
+                const T ar = Sr[ar_row][kc], ai = Si[ar_row][kc];
+                const T br = Jr[kc][bq], bi = Ji[kc][bq];
+                re[u] = MF::op(ar, br, re[u]);
+                re[u] = MF::op(-ai, bi, re[u]);
+                im[u] = MF::op(ar, bi, im[u]);
+                im[u] = MF::op(ai, br, im[u]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int t = wave + 4 * u;
+            const int ti = t / NT, tj = t % NT;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int rr = ti * 16 + MF::row(lane, v), cc = tj * 16 + lane % 16;
+                Sr[rr][cc] = re[u][v];
+                Si[rr][cc] = im[u][v];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < JRS * NC; e += 256) {
+            const int c = e / JRS, rr = e % JRS, row = r0 + rr;
+            if (c < nc && row < r_end) X[(size_t)cols[c] * M + row] = mk<T>(Sr[rr][c], Si[rr][c]);
+        }
+    }
+}
+
+static int chunks_for(int rows, int npairs, int target) {
+    int maxc = (rows + JRS - 1) / JRS;
+    int c = (target + npairs - 1) / npairs;
+    if (c > maxc) c = maxc;
+    if (c < 1) c = 1;
+    return c;
+}
+static int rows_per_chunk(int rows, int nch) {
+    int steps = (rows + JRS - 1) / JRS;
+    return JRS * ((steps + nch - 1) / nch);
+}
+
+template <typename T, int NC>
+static void round3(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
+                   int inner_max, void *partial, void *J, int *rotflag, int *rot_counter,
+                   hipStream_t s) {
+    const int npairs = nb / 2;
+    const int nchG = chunks_for(m, npairs, 512);
+    const int rpcG = rows_per_chunk(m, nchG);
+    const int nchG_eff = (m + rpcG - 1) / rpcG;
+    k_jgram<T, NC><<<dim3(npairs, nchG_eff), 256, 0, s>>>((const cx<T> *)W, m, n, w, nb, rnd, rpcG,
+                                                        (cx<T> *)partial);
+    k_jeig<T, NC><<<npairs, 256, 0, s>>>((const cx<T> *)partial, nchG_eff, n, w, nb, rnd, (T)tol,
+                                         inner_max, (cx<T> *)J, rotflag, rot_counter);
+    const int nchW = chunks_for(m, npairs, 512), rpcW = rows_per_chunk(m, nchW);
+    const int nchV = chunks_for(n, npairs, 512), rpcV = rows_per_chunk(n, nchV);
+    const int nW = (m + rpcW - 1) / rpcW, nV = (n + rpcV - 1) / rpcV;
+    k_japply<T, NC><<<dim3(npairs, nW + nV), 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb, rnd,
+                                                        nW, rpcW, rpcV, (const cx<T> *)J, rotflag);
+}
+
+// Workspace (in complex elements) needed by launch_jacobi_round3.
+size_t jacobi_round3_partial_elems(int m, int n, int w) {
+    const int nc = 2 * w <= 32 ? 32 : 64;
+    int nb = (n + w - 1) / w;
+    nb += nb & 1;
+    const int npairs = nb / 2;
+    const int nchG = chunks_for(m, npairs, 512);
+    const int rpcG = rows_per_chunk(m, nchG);
+    const int nchG_eff = (m + rpcG - 1) / rpcG;
+    return (size_t)npairs * nchG_eff * nc * nc;
+}
+size_t jacobi_round3_j_elems(int n, int w) {
+    const int nc = 2 * w <= 32 ? 32 : 64;
+    int nb = (n + w - 1) / w;
+    nb += nb & 1;
+    return (size_t)(nb / 2) * nc * nc;
+}
+
+template <typename T>
+void launch_jacobi_round3(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
+                          int inner_max, void *partial, void *J, int *rotflag, int *rot_counter,
+                          hipStream_t s) {
+    if (2 * w <= 32)
+        round3<T, 32>(W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag, rot_counter, s);
+    else
+        round3<T, 64>(W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag, rot_counter, s);
+}
+
+template void launch_jacobi_round3<float>(void *, int, void *, int, int, int, int, double, int,
+                                          void *, void *, int *, int *, hipStream_t);
+template void launch_jacobi_round3<double>(void *, int, void *, int, int, int, int, double, int,
+                                           void *, void *, int *, int *, hipStream_t);

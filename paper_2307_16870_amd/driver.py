@@ -83,19 +83,32 @@ class EAState:
     def site(self, i):
         return B.mps_get_site(self.h, i)
 
+    def reset(self, local=None):
+        self.warnings = 0
+        return B.mps_reset_product(self.h, local)
+
+    def profile(self, enable):
+        return B.mps_profile(self.h, enable)
+
+    def profile_read(self, family):
+        return B.mps_profile_read(self.h, family)
+
     # -------------------------------------------------------------- circuit
     def run(self, program, f_min=1.0, strategy=B.EA_GLOBAL, schedule=True):
         """Apply a ``circuits.Program``; returns the number of warnings."""
         if schedule:
             self.set_schedule(f_min, max(1, program.n_2q), strategy)
         for layer in program.layers:
-            for op in layer:
-                if op.width == 1:
-                    self.apply_1q(op.site, op.mat)
-            twos = [op for op in layer if op.width == 2]
-            if twos:
-                rc, _ = self.apply_layer([op.site for op in twos],
-                                         np.stack([op.mat for op in twos]))
-                if rc > 0:
-                    self.warnings += 1
+            self.run_layer(layer)
         return self.warnings
+
+    def run_layer(self, layer):
+        """One-qubit ops of the layer in order, then its two-qubit ops."""
+        for op in layer:
+            if op.width == 1:
+                self.apply_1q(op.site, op.mat)
+        twos = [op for op in layer if op.width == 2]
+        if twos:
+            rc, _ = self.apply_layer([op.site for op in twos], np.stack([op.mat for op in twos]))
+            if rc > 0:
+                self.warnings += 1

@@ -75,13 +75,18 @@ def test_truncating_run_fp64(f_min, seed):
     assert F >= f_min * (1 - 1e-12)
 
 
-@pytest.mark.parametrize("chis", [(37, 70, 45), (100, 128, 90), (160, 150, 129)])
-def test_single_update_multiworkgroup(chis):
+_SINGLE_CACHE = {}
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("chis", [(37, 70, 45), (100, 128, 90), (160, 150, 129), (300, 260, 333)])
+def test_single_update_multiworkgroup(chis, kernel):
     """One update on loaded random tensors large enough for the multi-
     workgroup Jacobi (2*chi > 64) with a ragged tail; compares f, T, k and the
-    gauge-free product A_i A_{i+1} after truncation."""
+    gauge-free product A_i A_{i+1} after truncation.  kernel 0: three-kernel
+    MFMA round; 1: fused round."""
     chiL, chiM, chiR = chis
-    _say("case: single update", chis)
+    _say("case: single update", chis, "kernel", kernel)
     n = 4
     dims = [1, chiL, chiM, chiR, 1]
     # outer sites must be able to carry the bonds: give them d = 2 only in
@@ -89,10 +94,13 @@ def test_single_update_multiworkgroup(chis):
     tens = C.random_mps_tensors(dims, 2, seed=sum(chis))
     rng = np.random.default_rng(5)
     G = C.haar_unitary(rng)
-    o = OracleMPS(n, "pure", keep_spectra=True)
-    o.load(tens, 1)
-    rec = o.apply_2q(1, G, 0.98)
+    if chis not in _SINGLE_CACHE:
+        o = OracleMPS(n, "pure", keep_spectra=True)
+        o.load(tens, 1)
+        _SINGLE_CACHE[chis] = (o, o.apply_2q(1, G, 0.98))
+    o, rec = _SINGLE_CACHE[chis]
     with P.EAState(n, "pure", "c128") as st:
+        st.set_option(P.EA_OPT_JACOBI_KERNEL, kernel)
         st.load(tens, 1)
         rc, f = st.apply_2q(1, G, 0.98)
         glog = st.gate_log()
