@@ -84,9 +84,11 @@ enum ea_option {
     EA_OPT_TAU = 2,          /* numerical-zero cutoff tau*s_0; 1e-13 (FP64), 2e-6 (FP32) */
     EA_OPT_BLOCK = 3,        /* Jacobi column-block width (0 = automatic) */
     EA_OPT_CHI_MAX = 4,      /* cap on kept rank; 0 = none */
-    EA_OPT_INNER_SWEEPS = 5, /* rotation sweeps over a block pair's Gram per round (default 2) */
-    EA_OPT_JACOBI_KERNEL = 6 /* 0: Gram / rotations / apply as three kernels (MFMA);
+    EA_OPT_INNER_SWEEPS = 5, /* rotation sweeps over a block pair's Gram per round (default 1) */
+    EA_OPT_JACOBI_KERNEL = 6,/* 0: Gram / rotations / apply as three kernels (MFMA);
                                 1: one fused kernel per round (vector ALU) */
+    EA_OPT_ROT_THREADS = 7   /* threads of the per-pair rotation kernel: 64, 128, 256,
+                                512 (default) or 1024 */
 };
 
 /* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */
@@ -200,14 +202,18 @@ int mps_reset_product(ea_mps *h, const double *local);
  * unaffected). */
 enum ea_kfamily {
     EA_K_THETA = 0,        /* two-site contraction + gate */
-    EA_K_JACOBI_ROUND = 1, /* one round of the multi-workgroup block Jacobi */
-    EA_K_JACOBI_SMALL = 2, /* single-workgroup Jacobi (<= 64 columns) */
-    EA_K_NORMS = 3,        /* singular values as column norms */
-    EA_K_TRUNC = 4,        /* sort + kept-rank search */
-    EA_K_GATHER = 5,       /* write-back of the new site tensors */
-    EA_K_GEMM = 6,         /* absorb products (centre moves, chain contraction) */
-    EA_K_OTHER = 7,
-    EA_K_COUNT = 8
+    EA_K_JGRAM = 1,        /* Jacobi round, part 1: MFMA partial Gram matrices */
+    EA_K_JROT = 2,         /* Jacobi round, part 2: rotations of each block pair */
+    EA_K_JAPPLY = 3,       /* Jacobi round, part 3: MFMA apply to W and V */
+    EA_K_JFUSED = 4,       /* Jacobi round as one fused kernel (vector ALU) */
+    EA_K_JSMALL = 5,       /* single-workgroup Jacobi (<= 64 columns) */
+    EA_K_NORMS = 6,        /* singular values as column norms */
+    EA_K_TRUNC = 7,        /* sort + kept-rank search */
+    EA_K_GATHER = 8,       /* write-back of the new site tensors */
+    EA_K_GEMM = 9,         /* absorb products (centre moves, chain contraction) */
+    EA_K_OTHER = 10,
+    EA_K_MOVE = 11,        /* whole centre moves (overlaps the families above) */
+    EA_K_COUNT = 12
 };
 
 /* enable = 1: start timing every kernel launch of this handle with a pair of

@@ -21,7 +21,7 @@ EA_OK, EA_WARN_CAPPED, EA_WARN_NOCONV = 0, 1, 2
 EA_EINVAL, EA_ERANGE, EA_ENOMEM, EA_EHIP, EA_ETOOBIG = -1, -2, -3, -4, -5
 EA_NAIVE, EA_GLOBAL, EA_NEAREST = 0, 1, 2
 EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
-EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL = 5, 6
+EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL, EA_OPT_ROT_THREADS = 5, 6, 7
 
 SYMBOLS = [
     "mps_init_product", "mps_free", "mps_set_option", "mps_set_schedule", "mps_apply_1q",
@@ -30,10 +30,11 @@ SYMBOLS = [
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read", "ea_last_error",
 ]
 
-EA_K_THETA, EA_K_JACOBI_ROUND, EA_K_JACOBI_SMALL, EA_K_NORMS = 0, 1, 2, 3
-EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_COUNT = 4, 5, 6, 7, 8
-K_FAMILY_NAMES = ["theta", "jacobi_round", "jacobi_small", "norms", "trunc", "gather", "gemm",
-                  "other"]
+K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
+                  "jacobi_small", "norms", "trunc", "gather", "gemm", "other", "centre_move"]
+(EA_K_THETA, EA_K_JGRAM, EA_K_JROT, EA_K_JAPPLY, EA_K_JFUSED, EA_K_JSMALL, EA_K_NORMS,
+ EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_MOVE) = range(12)
+EA_K_COUNT = 12
 
 
 class EAError(RuntimeError):

@@ -52,7 +52,7 @@ struct ea_mps {
     int strategy = EA_GLOBAL;
     // workspace
     DevBuf jpart, jmat, jflag;
-    int inner_round = 2, jkernel = 0;
+    int inner_round = 1, jkernel = 0, rot_threads = 512;
     DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
     ea_dev_rec *rec_host = nullptr;
     int *int_host = nullptr;
@@ -246,14 +246,14 @@ int svd_core(ea_mps *h, int m, int n) {
         launch_eye<T>(h->V.p, n, h->stream);
     }
     if (n <= 64) {
-        ProfScope ps(h, EA_K_JACOBI_SMALL, 0.0, 2.0 * c * (m + n) * (double)n);
+        ProfScope ps(h, EA_K_JSMALL, 0.0, 2.0 * c * (m + n) * (double)n);
         launch_jacobi_single<T>(h->W.p, m, h->V.p, n, tol, h->inner_max, h->max_sweeps,
                                 sweeps_dev, h->stream);
         LAUNCHCHK(h);
         return EA_OK;
     }
     const bool three = h->jkernel == 0;
-    int w = h->block > 0 ? h->block : (three ? (n <= 256 ? 16 : 32) : (n <= 256 ? 8 : 16));
+    int w = h->block > 0 ? h->block : (three ? 16 : (n <= 256 ? 8 : 16));
     if (2 * w > 64) w = 32;
     const int ncmax = 2 * w <= 16 ? 16 : (2 * w <= 32 ? 32 : 64);
     int nb = (n + w - 1) / w;
@@ -267,25 +267,42 @@ int svd_core(ea_mps *h, int m, int n) {
     for (int sw = 0; sw < h->max_sweeps; ++sw) {
         launch_fill_int(counter, 1, 0, h->stream);
         for (int rnd = 0; rnd < nb - 1; ++rnd) {
-            // algorithmic work of one round: every column pair block forms its
-            // Hermitian Gram (4 m nc^2 flops) and rotates nc columns of W and V
-            // (8 (m + n) nc^2 flops); W and V are read and written once
-            double fl = 0.0;
+            // algorithmic work of one round: every column block pair forms its
+            // Hermitian Gram matrix (4 m nc^2 flops) and rotates its nc columns of W
+            // and V (8 (m + n) nc^2 flops)
+            double fl2 = 0.0;
             for (int p = 0; p < nb / 2; ++p) {
                 const int a = p == 0 ? 0 : (p - 1 + rnd) % (nb - 1) + 1;
                 const int bq = nb - 1 - p;
                 const int b = bq == 0 ? 0 : (bq - 1 + rnd) % (nb - 1) + 1;
                 const int nc = std::max(0, std::min(w, n - a * w)) + std::max(0, std::min(w, n - b * w));
-                fl += (4.0 * m + 8.0 * (m + n)) * nc * (double)nc;
+                fl2 += (double)nc * nc;
             }
-            ProfScope ps(h, EA_K_JACOBI_ROUND, fl, 2.0 * c * (m + n) * (double)n);
-            if (three)
-                launch_jacobi_round3<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                        h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                        h->stream);
-            else
+            if (three) {
+                {
+                    ProfScope ps(h, EA_K_JGRAM, 4.0 * m * fl2, c * m * (double)n);
+                    launch_jacobi_part<T>(0, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
+                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                          h->rot_threads, h->stream);
+                }
+                {
+                    ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * 64.0 * 64.0);
+                    launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
+                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                          h->rot_threads, h->stream);
+                }
+                {
+                    ProfScope ps(h, EA_K_JAPPLY, 8.0 * (m + n) * fl2, 2.0 * c * (m + n) * (double)n);
+                    launch_jacobi_part<T>(2, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
+                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                          h->rot_threads, h->stream);
+                }
+            } else {
+                ProfScope ps(h, EA_K_JFUSED, (4.0 * m + 8.0 * (m + n)) * fl2,
+                             2.0 * c * (m + n) * (double)n);
                 launch_jacobi_round<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, 6, ncmax, counter,
                                        h->stream);
+            }
         }
         LAUNCHCHK(h);
         HIPCHK(h, hipMemcpyAsync(h->int_host, counter, sizeof(int), hipMemcpyDeviceToHost,
@@ -420,8 +437,14 @@ int move_left(ea_mps *h) {
 
 template <typename T>
 int move_center(ea_mps *h, int j) {
-    while (h->center < j) TRY(move_right<T>(h));
-    while (h->center > j) TRY(move_left<T>(h));
+    while (h->center < j) {
+        ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
+        TRY(move_right<T>(h));
+    }
+    while (h->center > j) {
+        ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
+        TRY(move_left<T>(h));
+    }
     return EA_OK;
 }
 
@@ -869,6 +892,11 @@ int mps_set_option(ea_mps *h, int option, double value) {
     case EA_OPT_JACOBI_KERNEL:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi kernel must be 0 or 1");
         h->jkernel = (int)value;
+        return EA_OK;
+    case EA_OPT_ROT_THREADS:
+        if (value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
+            return set_err(EA_EINVAL, "rotation threads must be 64, 128, 256, 512 or 1024");
+        h->rot_threads = (int)value;
         return EA_OK;
     default:
         return set_err(EA_EINVAL, "unknown option %d", option);

@@ -116,10 +116,11 @@ void launch_vec_to_rho(const void *vec, void *rho, int n, hipStream_t s);
 // x[i] *= (re + i im), i < n.
 template <typename T>
 void launch_scale(void *x, size_t n, double re, double im, hipStream_t s);
-// Three-kernel round (MFMA Gram, per-pair rotations, MFMA apply); 2w <= 64.
+// One part of a three-kernel round (2w <= 64): part 0 = MFMA partial Gram
+// matrices, 1 = per-pair rotations, 2 = MFMA apply to W and V.
 template <typename T>
-void launch_jacobi_round3(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
-                          int inner_max, void *partial, void *J, int *rotflag, int *rot_counter,
-                          hipStream_t s);
+void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
+                        double tol, int inner_max, void *partial, void *J, int *rotflag,
+                        int *rot_counter, int rot_threads, hipStream_t s);
 size_t jacobi_round3_partial_elems(int m, int n, int w);
 size_t jacobi_round3_j_elems(int n, int w);

@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
     }
 }
 
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial, int nchunks,
+template <typename T, int NC, int NTH>
+__global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial, int nchunks,
                                               int n, int w, int nb, int rnd, T tol,
                                               int inner_max, cx<T> *__restrict__ Jout,
                                               int *__restrict__ rotflag,
@@ -149,12 +149,12 @@ __global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial,
     __shared__ cx<T> re_[NP];
     __shared__ int rp_[NP], rq_[NP], rdo_[NP];
     __shared__ int cols[NC];
-    __shared__ int nrot_sh;
-    const int tid = threadIdx.x, nth = 256, pair = blockIdx.x;
-    const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, nth);
+    __shared__ int nrot_sh[2];
+    const int tid = threadIdx.x, pair = blockIdx.x;
+    const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, NTH);
     // sum the partial Gram tiles (upper triangle) in a fixed order
     const cx<T> *src = partial + (size_t)pair * nchunks * NC * NC;
-    for (int e = tid; e < NC * NC; e += nth) {
+    for (int e = tid; e < NC * NC; e += NTH) {
         const int p = e / NC, q = e % NC;
         if (p <= q) {
             double sx = 0.0, sy = 0.0;
@@ -169,15 +169,16 @@ __global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial,
         }
         J[p][q] = mk<T>(p == q ? T(1) : T(0), T(0));
     }
+    if (tid < 2) nrot_sh[tid] = 0;
     __syncthreads();
     const int nce = nc + (nc & 1);
     const int npairs = nce / 2;
     int first = 0;
     if (nc >= 2) {
         for (int isw = 0; isw < inner_max; ++isw) {
-            if (tid == 0) nrot_sh = 0;
-            __syncthreads();
+            const int slot = isw & 1;
             for (int step = 0; step < nce - 1; ++step) {
+                // rotation of each disjoint pair of this step, from the current G
                 if (tid < npairs) {
                     int p = rr_player(tid, step, nce), q = rr_player(nce - 1 - tid, step, nce);
                     if (p > q) {
@@ -192,7 +193,8 @@ __global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial,
                         const T g = sqrt(norm2(ga));
                         if (g > T(0) && g > tol * sqrt(al * be)) {
                             const T zeta = (be - al) / (T(2) * g);
-                            const T t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + hypot(T(1), zeta));
+                            const T az = fabs(zeta);
+                            const T t = (zeta >= T(0) ? T(1) : T(-1)) / (az + (az < T(1e15) ? sqrt(T(1) + az * az) : az));
                             const T c = T(1) / sqrt(T(1) + t * t);
                             rc_[tid] = c;
                             rs_[tid] = c * t;
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial,
                             ra_[tid] = al;
                             rb_[tid] = be;
                             dd = 1;
-                            atomicAdd(&nrot_sh, 1);
+                            atomicAdd(&nrot_sh[slot], 1);
                         }
                     }
                     rp_[tid] = p;
@@ -209,50 +211,66 @@ __global__ __launch_bounds__(256) void k_jeig(const cx<T> *__restrict__ partial,
                     rdo_[tid] = dd;
                 }
                 __syncthreads();
-                for (int e = tid; e < npairs * nc; e += nth) {
-                    const int pi = e / nc, row = e % nc;
-                    if (rdo_[pi]) {
-                        const int p = rp_[pi], q = rq_[pi];
-                        const T c = rc_[pi], s = rs_[pi];
-                        const cx<T> ee = re_[pi];
-                        const cx<T> gp = G[row][p], gq = ee * G[row][q];
-                        G[row][p] = c * gp - s * gq;
-                        G[row][q] = s * gp + c * gq;
-                        const cx<T> jp = J[row][p], jq = ee * J[row][q];
+                // G <- M^H G M on 2x2 blocks (row pair a, column pair b); each block
+                // needs only its own four entries, so one pass suffices.
+                for (int e = tid; e < npairs * npairs; e += NTH) {
+                    const int a = e / npairs, b = e % npairs;
+                    const int da = rdo_[a], db = rdo_[b];
+                    if (!da && !db) continue;
+                    const int pa = rp_[a], qa = rq_[a], pb = rp_[b], qb = rq_[b];
+                    if (a == b) {  // rotated pair: exact diagonal
+                        G[pa][qa] = zero_cx<T>();
+                        G[qa][pa] = zero_cx<T>();
+                        G[pa][pa] = mk<T>(ra_[a] - rtg_[a], T(0));
+                        G[qa][qa] = mk<T>(rb_[a] + rtg_[a], T(0));
+                        continue;
+                    }
+                    const bool va = qa < nc, vb = qb < nc;
+                    cx<T> g00 = G[pa][pb], g01 = vb ? G[pa][qb] : zero_cx<T>();
+                    cx<T> g10 = va ? G[qa][pb] : zero_cx<T>(), g11 = (va && vb) ? G[qa][qb] : zero_cx<T>();
+                    if (db) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
+                        const T c = rc_[b], s = rs_[b];
+                        const cx<T> ee = re_[b];
+                        const cx<T> t01 = ee * g01, t11 = ee * g11;
+                        const cx<T> n00 = c * g00 - s * t01, n01 = s * g00 + c * t01;
+                        const cx<T> n10 = c * g10 - s * t11, n11 = s * g10 + c * t11;
+                        g00 = n00; g01 = n01; g10 = n10; g11 = n11;
+                    }
+                    if (da) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
+                        const T c = rc_[a], s = rs_[a];
+                        const cx<T> ec = conj(re_[a]);
+                        const cx<T> t10 = ec * g10, t11 = ec * g11;
+                        const cx<T> n00 = c * g00 - s * t10, n10 = s * g00 + c * t10;
+                        const cx<T> n01 = c * g01 - s * t11, n11 = s * g01 + c * t11;
+                        g00 = n00; g01 = n01; g10 = n10; g11 = n11;
+                    }
+                    G[pa][pb] = g00;
+                    if (vb) G[pa][qb] = g01;
+                    if (va) G[qa][pb] = g10;
+                    if (va && vb) G[qa][qb] = g11;
+                }
+                // J <- J M on the rotated column pairs
+                for (int e = tid; e < npairs * nc; e += NTH) {
+                    const int b = e / nc, row = e % nc;
+                    if (rdo_[b]) {
+                        const int p = rp_[b], q = rq_[b];
+                        const T c = rc_[b], s = rs_[b];
+                        const cx<T> jp = J[row][p], jq = re_[b] * J[row][q];
                         J[row][p] = c * jp - s * jq;
                         J[row][q] = s * jp + c * jq;
                     }
                 }
                 __syncthreads();
-                for (int e = tid; e < npairs * nc; e += nth) {
-                    const int pi = e / nc, col = e % nc;
-                    if (rdo_[pi]) {
-                        const int p = rp_[pi], q = rq_[pi];
-                        const T c = rc_[pi], s = rs_[pi];
-                        const cx<T> ec = conj(re_[pi]);
-                        const cx<T> gp = G[p][col], gq = ec * G[q][col];
-                        G[p][col] = c * gp - s * gq;
-                        G[q][col] = s * gp + c * gq;
-                    }
-                }
-                __syncthreads();
-                if (tid < npairs && rdo_[tid]) {
-                    const int p = rp_[tid], q = rq_[tid];
-                    G[p][q] = zero_cx<T>();
-                    G[q][p] = zero_cx<T>();
-                    G[p][p] = mk<T>(ra_[tid] - rtg_[tid], T(0));
-                    G[q][q] = mk<T>(rb_[tid] + rtg_[tid], T(0));
-                }
-                __syncthreads();
             }
-            const int nr = nrot_sh;
-            __syncthreads();
+            const int nr = nrot_sh[slot];
             if (isw == 0) first = nr;
+            if (tid == 0) nrot_sh[slot ^ 1] = 0;  // counter of the next sweep
+            __syncthreads();
             if (nr == 0) break;
         }
     }
     cx<T> *jo = Jout + (size_t)pair * NC * NC;
-    for (int e = tid; e < NC * NC; e += nth) {
+    for (int e = tid; e < NC * NC; e += NTH) {
         const int p = e / NC, q = e % NC;
         jo[e] = (p < nc && q < nc) ? J[p][q] : zero_cx<T>();
     }
@@ -345,23 +363,37 @@ static int rows_per_chunk(int rows, int nch) {
     return JRS * ((steps + nch - 1) / nch);
 }
 
+
 template <typename T, int NC>
-static void round3(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
-                   int inner_max, void *partial, void *J, int *rotflag, int *rot_counter,
-                   hipStream_t s) {
+static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
+                       double tol, int inner_max, void *partial, void *J, int *rotflag,
+                       int *rot_counter, int rot_threads, hipStream_t s) {
     const int npairs = nb / 2;
     const int nchG = chunks_for(m, npairs, 512);
     const int rpcG = rows_per_chunk(m, nchG);
     const int nchG_eff = (m + rpcG - 1) / rpcG;
-    k_jgram<T, NC><<<dim3(npairs, nchG_eff), 256, 0, s>>>((const cx<T> *)W, m, n, w, nb, rnd, rpcG,
-                                                        (cx<T> *)partial);
-    k_jeig<T, NC><<<npairs, 256, 0, s>>>((const cx<T> *)partial, nchG_eff, n, w, nb, rnd, (T)tol,
-                                         inner_max, (cx<T> *)J, rotflag, rot_counter);
-    const int nchW = chunks_for(m, npairs, 512), rpcW = rows_per_chunk(m, nchW);
-    const int nchV = chunks_for(n, npairs, 512), rpcV = rows_per_chunk(n, nchV);
-    const int nW = (m + rpcW - 1) / rpcW, nV = (n + rpcV - 1) / rpcV;
-    k_japply<T, NC><<<dim3(npairs, nW + nV), 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb, rnd,
-                                                        nW, rpcW, rpcV, (const cx<T> *)J, rotflag);
+    if (part == 0) {
+        k_jgram<T, NC><<<dim3(npairs, nchG_eff), 256, 0, s>>>((const cx<T> *)W, m, n, w, nb, rnd,
+                                                            rpcG, (cx<T> *)partial);
+    } else if (part == 1) {
+#define EA_JEIG(NTH)                                                                          \
+    k_jeig<T, NC, NTH><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, w, nb, rnd,   \
+                                              (T)tol, inner_max, (cx<T> *)J, rotflag,        \
+                                              rot_counter)
+        if (rot_threads <= 64) EA_JEIG(64);
+        else if (rot_threads <= 128) EA_JEIG(128);
+        else if (rot_threads <= 256) EA_JEIG(256);
+        else if (rot_threads <= 512) EA_JEIG(512);
+        else EA_JEIG(1024);
+#undef EA_JEIG
+    } else {
+        const int nchW = chunks_for(m, npairs, 512), rpcW = rows_per_chunk(m, nchW);
+        const int nchV = chunks_for(n, npairs, 512), rpcV = rows_per_chunk(n, nchV);
+        const int nW = (m + rpcW - 1) / rpcW, nV = (n + rpcV - 1) / rpcV;
+        k_japply<T, NC><<<dim3(npairs, nW + nV), 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb,
+                                                            rnd, nW, rpcW, rpcV,
+                                                            (const cx<T> *)J, rotflag);
+    }
 }
 
 // Workspace (in complex elements) needed by launch_jacobi_round3.
@@ -383,16 +415,18 @@ size_t jacobi_round3_j_elems(int n, int w) {
 }
 
 template <typename T>
-void launch_jacobi_round3(void *W, int m, void *V, int n, int w, int nb, int rnd, double tol,
-                          int inner_max, void *partial, void *J, int *rotflag, int *rot_counter,
-                          hipStream_t s) {
+void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
+                        double tol, int inner_max, void *partial, void *J, int *rotflag,
+                        int *rot_counter, int rot_threads, hipStream_t s) {
     if (2 * w <= 32)
-        round3<T, 32>(W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag, rot_counter, s);
+        round_part<T, 32>(part, W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag,
+                          rot_counter, rot_threads, s);
     else
-        round3<T, 64>(W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag, rot_counter, s);
+        round_part<T, 64>(part, W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag,
+                          rot_counter, rot_threads, s);
 }
 
-template void launch_jacobi_round3<float>(void *, int, void *, int, int, int, int, double, int,
-                                          void *, void *, int *, int *, hipStream_t);
-template void launch_jacobi_round3<double>(void *, int, void *, int, int, int, int, double, int,
-                                           void *, void *, int *, int *, hipStream_t);
+template void launch_jacobi_part<float>(int, void *, int, void *, int, int, int, int, double, int,
+                                        void *, void *, int *, int *, int, hipStream_t);
+template void launch_jacobi_part<double>(int, void *, int, void *, int, int, int, int, double,
+                                         int, void *, void *, int *, int *, int, hipStream_t);
