@@ -309,6 +309,9 @@ int svd_core(ea_mps *h, int m, int n) {
                                  h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
         ++sweeps;
+        // algorithmic work of the rotations of this sweep: each rotation updates
+        // two rows of the Hermitian Gram matrix and two columns of J (48 nc flops)
+        if (h->prof_on && three) h->prof_flops[EA_K_JROT] += 48.0 * 2 * w * (double)h->int_host[0];
         if (h->int_host[0] == 0) {
             conv = 1;
             break;
