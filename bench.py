@@ -73,6 +73,70 @@ def cpu_baseline(prog, f_min, chi_max, n_layers, budget_s):
     }
 
 
+def bench_batched(args, torch, C, P):
+    """Independent circuits of the batched workload (N ~ U{20..80}, depth ~
+    U{10..40}, capped at --max-depth, F_min = 0.99, chi <= 1024), advanced layer
+    by layer together (one stream per state) and, for comparison, one after
+    the other."""
+    import numpy as np
+    progs = C.batched_programs(64)[: args.circuits]
+    for p in progs:
+        p.layers = p.layers[: args.max_depth]
+    n_upd = sum(p.n_2q for p in progs)
+
+    def layer_args(t):
+        sites, ops = [], []
+        for p in progs:
+            layer = p.layers[t] if t < len(p.layers) else []
+            sites.append([op.site for op in layer])
+            ops.append(np.stack([op.mat for op in layer]) if layer else np.zeros((0, 4, 4), complex))
+        return sites, ops
+
+    states = [P.EAState(p.n_sites, "pure", args.prec, chi_max=1024) for p in progs]
+    depth = max(len(p.layers) for p in progs)
+    largs = [layer_args(t) for t in range(depth)]
+
+    def run_batched():
+        for st, p in zip(states, progs):
+            st.reset()
+            st.set_schedule(0.99, p.n_2q)
+        for t in range(depth):
+            P.mps_apply_layer_batched([s.h for s in states], *largs[t])
+
+    def run_sequential():
+        for st, p in zip(states, progs):
+            st.reset()
+            st.run(p, 0.99)
+
+    run_batched()  # loads code objects, sizes buffers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_batched()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log(f"batched {tb:.2f}s")
+    t0 = time.perf_counter()
+    run_sequential()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    log(f"sequential {ts:.2f}s")
+    Fs = [s.fidelity_estimate()[0] for s in states]
+    out = {
+        "metric": "2-site gate updates/s, independent circuits advanced together, 1 GPU",
+        "value": n_upd / tb, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000 * tb, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.prec == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched-{len(progs)}-circuits-N20to80-depth<= {args.max_depth}",
+                   "circuits": len(progs), "updates": n_upd, "f_min": 0.99, "chi_max": 1024},
+        "sequential_updates_per_s": n_upd / ts, "speedup_batched_vs_sequential": ts / tb,
+        "circuits_with_P_ge_0.99": int(sum(F >= 0.99 for F in Fs)),
+    }
+    for s in states:
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +149,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-layers", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--workload", default="brickwork50", choices=["brickwork50", "batched"],
+                    help="brickwork50: the 50-qubit depth-20 circuit (default); batched: "
+                         "independent circuits of the batched workload advanced together")
+    ap.add_argument("--circuits", type=int, default=16, help="batched: number of circuits")
+    ap.add_argument("--max-depth", type=int, default=12, help="batched: depth cap per circuit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -98,6 +167,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.init()
+    if args.workload == "batched":
+        return bench_batched(args, torch, C, P)
     stream = torch.cuda.current_stream()
     prog, cfg = C.config_program(2, depth=args.depth)
     f_min, chi_max = cfg["f_min"], cfg["chi_max"]

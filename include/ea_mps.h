@@ -111,7 +111,9 @@ typedef struct ea_gate_record {
  *  (0 = no cap, end of Sec. VI).
  *  local: NULL for |0...0> (pure) or |0><0|^N (mixed), else n_sites*d complex
  *  numbers, the d-vector of each site (vec(rho_i) for EA_MIXED).
- *  hip_stream: hipStream_t on which all work is enqueued (NULL = null stream).
+ *  hip_stream: hipStream_t on which all work is enqueued; NULL = a private
+ *  non-blocking stream created (default priority) and destroyed with the
+ *  handle.
  *  out: receives the handle.  Returns EA_EINVAL on bad arguments, EA_ENOMEM if
  *  device memory cannot be allocated. */
 int mps_init_product(int n_sites, int kind, int prec, int chi_max,
@@ -154,6 +156,21 @@ int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget,
  *  EA_EINVAL if two pairs overlap; then nothing is applied. */
 int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
                     const double *budgets, double *f_out);
+
+/* One layer on each of several independent states (batching: independent
+ * circuits share nothing, Sec. VI).  State b applies n_gates[b] two-site
+ * updates given, as for mps_apply_layer, by sites[b], ops[b] and budgets[b]
+ * (budgets may be NULL, or budgets[b] NULL, for the schedule); f_out may be
+ * NULL or hold n_states pointers (each NULL or n_gates[b] doubles).  The
+ * states advance concurrently, one host worker per state, each enqueuing on
+ * its own handle's stream, so their kernels overlap on the GPU; pass states
+ * created with distinct streams (or NULL streams, which give each handle a
+ * private stream).  status_out (n_states ints, may be NULL) receives each
+ * state's status.  Returns the most severe status (errors < warnings). */
+int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
+                            const int *const *sites, const double *const *ops,
+                            const double *const *budgets, double *const *f_out,
+                            int *status_out);
 
 /* Running estimate of the state fidelity, prod_i f_i (Eq. 12; Eq. 13 for
  * noisy runs, where it is a lower estimate).  Either pointer may be NULL. */

@@ -27,7 +27,8 @@ SYMBOLS = [
     "mps_init_product", "mps_free", "mps_set_option", "mps_set_schedule", "mps_apply_1q",
     "mps_apply_2q", "mps_apply_layer", "mps_fidelity_estimate", "mps_expect",
     "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
-    "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read", "ea_last_error",
+    "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
+    "mps_apply_layer_batched", "ea_last_error",
 ]
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
@@ -53,7 +54,7 @@ class GateRecord(ct.Structure):
 
 def load_library(path: str = LIB_PATH) -> ct.CDLL:
     if not os.path.exists(path):
-        raise ImportError(f"{path} not found: build it with `python -m paper_2307_16870_amd._build`")
+        raise ImportError(f"{path} not found: build it with `python paper_2307_16870_amd/_build.py`")
     lib = ct.CDLL(path)
     P, I, D, L, S = ct.c_void_p, ct.c_int, ct.c_double, ct.c_long, ct.c_size_t
     dp, ip = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)
@@ -76,10 +77,16 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_reset_product": (I, [P, dp]),
         "mps_profile": (I, [P, I]),
         "mps_profile_read": (I, [P, I, dp, ct.POINTER(ct.c_long), dp, dp]),
+        "mps_apply_layer_batched": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(dp),
+                                        ct.POINTER(dp), ct.POINTER(dp), ip]),
         "ea_last_error": (ct.c_char_p, []),
     }
     for name, (res, args) in sig.items():
-        fn = getattr(lib, name)
+        try:
+            fn = getattr(lib, name)
+        except AttributeError as e:
+            raise ImportError(f"{path} lacks {name}: rebuild with "
+                              "`python paper_2307_16870_amd/_build.py`") from e
         fn.restype = res
         fn.argtypes = args
     return lib
@@ -237,3 +244,35 @@ def mps_profile_read(h, family):
     _chk(_lib.mps_profile_read(h, int(family), ct.byref(ms), ct.byref(n), ct.byref(fl),
                                ct.byref(by)))
     return {"ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value}
+
+
+def mps_apply_layer_batched(handles, sites_list, ops_list, budgets_list=None):
+    """One layer on each state.  Returns (worst status, per-state statuses,
+    per-state achieved fidelities)."""
+    nb = len(handles)
+    hs = (ct.c_void_p * nb)(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
+    keep = []
+    ng = np.ascontiguousarray([len(s) for s in sites_list], dtype=np.int32)
+    sp = (ct.POINTER(ct.c_int) * nb)()
+    op = (ct.POINTER(ct.c_double) * nb)()
+    bp = (ct.POINTER(ct.c_double) * nb)()
+    fp = (ct.POINTER(ct.c_double) * nb)()
+    fs = []
+    for b in range(nb):
+        s = np.ascontiguousarray(np.asarray(sites_list[b], dtype=np.int32))
+        o = _c(ops_list[b])
+        keep += [s, o]
+        sp[b] = _ip(s)
+        op[b] = _dp(o)
+        if budgets_list is not None and budgets_list[b] is not None:
+            bb = np.ascontiguousarray(np.asarray(budgets_list[b], dtype=np.float64))
+            keep.append(bb)
+            bp[b] = _dp(bb)
+        f = np.zeros(len(s))
+        fs.append(f)
+        fp[b] = _dp(f)
+    st = np.zeros(nb, dtype=np.int32)
+    rc = _lib.mps_apply_layer_batched(nb, hs, _ip(ng), sp, op,
+                                      bp if budgets_list is not None else None, fp, _ip(st))
+    _chk(rc)
+    return rc, st.tolist(), fs

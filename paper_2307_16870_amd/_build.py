@@ -1,6 +1,8 @@
 """Build the HIP library ``_lib/libeamps.so`` for gfx950 with hipcc.
 
-Usage: ``python -m paper_2307_16870_amd._build`` (or ``__graft_entry__.build()``).
+Usage: ``python paper_2307_16870_amd/_build.py`` (or ``__graft_entry__.build()``);
+run it by path, not as ``-m``, so the package (which loads the library) is
+not imported first.
 Every call recompiles all sources (one hipcc process per source, in
 parallel) and links them into one shared library.
 """

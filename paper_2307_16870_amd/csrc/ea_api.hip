@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -40,6 +41,7 @@ struct ea_mps {
     bool f64 = true;
     size_t csz = 16;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
     std::vector<int> bond;  // n+1 entries, bond[0] = bond[n] = 1
     std::vector<DevBuf> site;
     DevBuf spare;
@@ -801,6 +803,14 @@ int mps_init_product(int n_sites, int kind, int prec, int chi_max, const double 
     h->csz = h->f64 ? 16 : 8;
     h->tau = h->f64 ? 1e-13 : 2e-6;
     h->stream = (hipStream_t)hip_stream;
+    if (!h->stream) {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return set_err(EA_EHIP, "stream creation failed");
+        }
+        h->own_stream = true;
+    }
     h->bond.assign(n_sites + 1, 1);
     h->site.resize(n_sites);
     auto bail = [&](int rc) {
@@ -862,6 +872,7 @@ void mps_free(ea_mps *h) {
     if (h->rec_host) (void)hipHostFree(h->rec_host);
     if (h->int_host) (void)hipHostFree(h->int_host);
     if (h->dbl_host) (void)hipHostFree(h->dbl_host);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
 
@@ -973,6 +984,42 @@ int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
         if (f_out) f_out[j] = f;
     }
     if (worst > 0) g_err = "warning during layer";
+    return worst;
+}
+
+int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
+                            const int *const *sites, const double *const *ops,
+                            const double *const *budgets, double *const *f_out,
+                            int *status_out) {
+    if (n_states < 0) return set_err(EA_EINVAL, "n_states < 0");
+    if (n_states == 0) return EA_OK;
+    if (!hs || !n_gates || !sites || !ops) return set_err(EA_EINVAL, "null argument");
+    for (int b = 0; b < n_states; ++b) {
+        TRY(check(hs[b]));
+        for (int c = 0; c < b; ++c)
+            if (hs[c] == hs[b]) return set_err(EA_EINVAL, "a state appears twice in the batch");
+    }
+    std::vector<int> rc(n_states, EA_OK);
+    std::vector<std::string> err(n_states);
+    auto work = [&](int b) {
+        rc[b] = mps_apply_layer(hs[b], n_gates[b], sites[b], ops[b], budgets ? budgets[b] : nullptr,
+                                f_out ? f_out[b] : nullptr);
+        if (rc[b] != EA_OK) err[b] = g_err;
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(n_states);
+    for (int b = 1; b < n_states; ++b) pool.emplace_back(work, b);
+    work(0);
+    for (auto &t : pool) t.join();
+    int worst = EA_OK, worst_b = -1;
+    for (int b = 0; b < n_states; ++b) {
+        if (status_out) status_out[b] = rc[b];
+        if ((rc[b] < 0 && (worst >= 0 || rc[b] < worst)) || (worst >= 0 && rc[b] > worst)) {
+            worst = rc[b];
+            worst_b = b;
+        }
+    }
+    if (worst_b >= 0) set_err(worst, "state %d: %s", worst_b, err[worst_b].c_str());
     return worst;
 }
 
