@@ -244,6 +244,45 @@ int mps_profile(ea_mps *h, int enable);
 int mps_profile_read(ea_mps *h, int family, double *ms_total, long *launches,
                      double *flops, double *bytes);
 
+/* ---- Differentiation (adjoint of the update with kept ranks frozen) ---- */
+
+enum ea_dop_kind {
+    EA_DOP_GATE1 = 0, /* fixed one-qubit unitary (mat: 2x2) */
+    EA_DOP_RY = 1,    /* RY(params[param]) = exp(-i t Y / 2) */
+    EA_DOP_RZ = 2,    /* RZ(params[param]) = exp(-i t Z / 2) */
+    EA_DOP_GATE2 = 3  /* fixed two-qubit gate on (site, site+1) (mat: 4x4) */
+};
+
+/* One operation of a differentiable circuit. */
+typedef struct ea_dop {
+    int32_t kind;      /* ea_dop_kind */
+    int32_t site;
+    int32_t param;     /* index into params (RY/RZ), else ignored */
+    int32_t layer_end; /* non-zero: a per-layer checkpoint follows this op */
+    double mat[32];    /* fixed gate, row-major complex: 2x2 (GATE1) or 4x4 (GATE2) */
+} ea_dop;
+
+/* Energy and gradient through the entanglement-aware simulation (pure
+ * states, EA_PURE handles of any precision).  Starting from |0...0>, applies
+ * the ops in order (two-site updates as mps_apply_2q, Sec. V-VI, with the
+ * global schedule for f_min if f_min < 1, else only numerically zero
+ * singular values are dropped), then evaluates
+ *     E = sum_t coefs[t] Re <O_t>
+ * with <O_t> as in mps_expect (Eq. 6), and the gradient dE/dparams with every
+ * kept rank frozen to the forward pass's choice: reverse passes through the
+ * one-qubit gates, the contraction (products with G^H), the truncated complex
+ * SVD (kept/discarded coupling through 1/(s_j^2 - s_i^2), broadened to
+ * (s_j^2 - s_i^2)/((s_j^2 - s_i^2)^2 + eta_rel s_0^4), phase term,
+ * renormalisation) and the centre moves.  The state is checkpointed at every
+ * layer end and each layer is recomputed once during the reverse pass.
+ * Outputs: E_out, grad_out (n_params doubles), lnP_out (ln of the fidelity
+ * estimate; any may be NULL except grad_out when n_params > 0).  On return the
+ * handle holds the final state of the circuit. */
+int mps_energy_grad(ea_mps *h, int n_ops, const ea_dop *ops, const double *params,
+                    int n_params, int n_terms, const int *sites, const int *widths,
+                    const double *term_ops, const double *coefs, double f_min,
+                    double eta_rel, double *E_out, double *grad_out, double *lnP_out);
+
 /* Message for the last non-zero status returned on this thread. */
 const char *ea_last_error(void);
 

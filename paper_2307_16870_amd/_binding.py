@@ -28,7 +28,7 @@ SYMBOLS = [
     "mps_apply_2q", "mps_apply_layer", "mps_fidelity_estimate", "mps_expect",
     "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
-    "mps_apply_layer_batched", "ea_last_error",
+    "mps_apply_layer_batched", "mps_energy_grad", "ea_last_error",
 ]
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
@@ -42,6 +42,15 @@ class EAError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (status {code})")
         self.code = code
+
+
+EA_DOP_GATE1, EA_DOP_RY, EA_DOP_RZ, EA_DOP_GATE2 = 0, 1, 2, 3
+
+
+class DOp(ct.Structure):
+    """One op of a differentiable circuit (ea_dop)."""
+    _fields_ = [("kind", ct.c_int32), ("site", ct.c_int32), ("param", ct.c_int32),
+                ("layer_end", ct.c_int32), ("mat", ct.c_double * 32)]
 
 
 class GateRecord(ct.Structure):
@@ -79,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_profile_read": (I, [P, I, dp, ct.POINTER(ct.c_long), dp, dp]),
         "mps_apply_layer_batched": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(dp),
                                         ct.POINTER(dp), ct.POINTER(dp), ip]),
+        "mps_energy_grad": (I, [P, I, ct.POINTER(DOp), dp, I, I, ip, ip, dp, dp, D, D, dp, dp, dp]),
         "ea_last_error": (ct.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -276,3 +286,52 @@ def mps_apply_layer_batched(handles, sites_list, ops_list, budgets_list=None):
                                       bp if budgets_list is not None else None, fp, _ip(st))
     _chk(rc)
     return rc, st.tolist(), fs
+
+
+def make_dops(ops):
+    """ops: list of (kind, site, param, layer_end, mat or None) -> ctypes array."""
+    arr = (DOp * len(ops))()
+    for j, (kind, site, param, layer_end, mat) in enumerate(ops):
+        arr[j].kind = kind
+        arr[j].site = site
+        arr[j].param = -1 if param is None else param
+        arr[j].layer_end = int(bool(layer_end))
+        if mat is not None:
+            m = _c(mat).view(np.float64).ravel()
+            for q in range(m.size):
+                arr[j].mat[q] = m[q]
+    return arr
+
+
+def hea_dops(n_qubits, n_layers):
+    """Hardware-efficient ansatz: per layer RY, RZ on every qubit (angles
+    2*(l*n+q) and 2*(l*n+q)+1), then CZ on brickwork pairs."""
+    cz = np.diag([1, 1, 1, -1]).astype(np.complex128)
+    ops = []
+    for l in range(n_layers):
+        for q in range(n_qubits):
+            ops.append((EA_DOP_RY, q, 2 * (l * n_qubits + q), False, None))
+            ops.append((EA_DOP_RZ, q, 2 * (l * n_qubits + q) + 1, False, None))
+        for i in range(l % 2, n_qubits - 1, 2):
+            ops.append((EA_DOP_GATE2, i, None, False, cz))
+        last = ops[-1]
+        ops[-1] = (last[0], last[1], last[2], True, last[4])
+    return ops
+
+
+def mps_energy_grad(h, dops, params, terms, f_min=1.0, eta_rel=0.0):
+    """E = sum_t c_t Re <O_t> after the circuit, and dE/dparams.  ``dops`` is
+    a list for make_dops or its result; ``terms`` a list of (site, width, op,
+    coef).  Returns (E, grad, lnP)."""
+    arr = dops if not isinstance(dops, list) else make_dops(dops)
+    prm = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+    sites = np.ascontiguousarray([t[0] for t in terms], dtype=np.int32)
+    widths = np.ascontiguousarray([t[1] for t in terms], dtype=np.int32)
+    ops = _c(np.concatenate([np.asarray(t[2], dtype=np.complex128).ravel() for t in terms]))
+    coefs = np.ascontiguousarray([t[3] for t in terms], dtype=np.float64)
+    grad = np.zeros(prm.size)
+    E, lnP = ct.c_double(), ct.c_double()
+    _chk(_lib.mps_energy_grad(h, len(arr), arr, _dp(prm), prm.size, len(terms), _ip(sites),
+                              _ip(widths), _dp(ops), _dp(coefs), float(f_min), float(eta_rel),
+                              ct.byref(E), _dp(grad), ct.byref(lnP)))
+    return E.value, grad, lnP.value

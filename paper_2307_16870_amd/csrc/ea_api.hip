@@ -1,778 +1,13 @@
 // Host side of the C ABI declared in include/ea_mps.h: handle, validation,
 // device memory, orthogonality-centre bookkeeping, the target schedule and
 // the orchestration of the kernels of one two-site update.
-#include "ea_mps.h"
-#include "ea_kernels.h"
+#include "ea_internal.h"
 
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <thread>
-#include <vector>
-
-namespace {
-
+namespace ea {
 thread_local std::string g_err;
+}  // namespace ea
 
-int set_err(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
-}  // namespace
-
-struct ea_mps {
-    int n = 0, d = 2, kind = EA_PURE, prec = EA_C128, chi_max = 0;
-    bool f64 = true;
-    size_t csz = 16;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    std::vector<int> bond;  // n+1 entries, bond[0] = bond[n] = 1
-    std::vector<DevBuf> site;
-    DevBuf spare;
-    int center = 0;
-    double lnP = 0.0, lnS = 0.0;
-    long g = 0;
-    bool has_sched = false;
-    double f_min = 1.0;
-    long n_total = 1;
-    int strategy = EA_GLOBAL;
-    // workspace
-    DevBuf jpart, jmat, jflag;
-    int inner_round = 1, jkernel = 0, rot_threads = 512;
-    DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
-    ea_dev_rec *rec_host = nullptr;
-    int *int_host = nullptr;
-    double *dbl_host = nullptr;
-    char *stage_host = nullptr;
-    size_t stage_cap = 0, stage_off = 0;
-    DevBuf stage_dev;
-    // options
-    double tol = 0.0;  // 0: m * eps
-    int max_sweeps = 40;
-    double tau = 1e-13;
-    int block = 0;
-    int inner_max = 12;
-    std::vector<ea_gate_record> log;
-    bool poisoned = false;
-    // per-launch event timing (mps_profile)
-    struct ProfRec {
-        hipEvent_t a, b;
-        int fam;
-        double flops, bytes;
-    };
-    bool prof_on = false;
-    std::vector<ProfRec> prof_pending;
-    std::vector<hipEvent_t> prof_pool;
-    double prof_ms[EA_K_COUNT] = {0}, prof_flops[EA_K_COUNT] = {0}, prof_bytes[EA_K_COUNT] = {0};
-    long prof_cnt[EA_K_COUNT] = {0};
-};
-
-namespace {
-
-#define HIPCHK(h, call)                                                                      \
-    do {                                                                                     \
-        hipError_t e_ = (call);                                                              \
-        if (e_ != hipSuccess) {                                                              \
-            (h)->poisoned = true;                                                            \
-            return set_err(EA_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));          \
-        }                                                                                    \
-    } while (0)
-
-#define LAUNCHCHK(h) HIPCHK(h, hipGetLastError())
-
-#define TRY(x)                     \
-    do {                           \
-        int rc_ = (x);             \
-        if (rc_ < 0) return rc_;   \
-    } while (0)
-
-hipEvent_t ev_get(ea_mps *h) {
-    if (!h->prof_pool.empty()) {
-        hipEvent_t e = h->prof_pool.back();
-        h->prof_pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Times the launches enqueued during its lifetime with an event pair.
-struct ProfScope {
-    ea_mps *h;
-    hipEvent_t a = nullptr;
-    int fam;
-    double fl, by;
-    ProfScope(ea_mps *h_, int fam_, double fl_, double by_) : h(h_), fam(fam_), fl(fl_), by(by_) {
-        if (h->prof_on && (a = ev_get(h)) != nullptr) (void)hipEventRecord(a, h->stream);
-    }
-    ~ProfScope() {
-        if (!a) return;
-        hipEvent_t b = ev_get(h);
-        if (!b) return;
-        (void)hipEventRecord(b, h->stream);
-        h->prof_pending.push_back({a, b, fam, fl, by});
-    }
-};
-
-// Accumulate completed event pairs (call after a stream synchronisation).
-void prof_harvest(ea_mps *h) {
-    for (auto &r : h->prof_pending) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-            h->prof_ms[r.fam] += ms;
-            h->prof_cnt[r.fam] += 1;
-            h->prof_flops[r.fam] += r.flops;
-            h->prof_bytes[r.fam] += r.bytes;
-        }
-        h->prof_pool.push_back(r.a);
-        h->prof_pool.push_back(r.b);
-    }
-    h->prof_pending.clear();
-}
-
-int ensure(ea_mps *h, DevBuf &b, size_t bytes) {
-    if (bytes <= b.bytes) return EA_OK;
-    if (b.p) {
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipFree(b.p));
-        b.p = nullptr;
-        b.bytes = 0;
-    }
-    size_t want = std::max(bytes, b.bytes + b.bytes / 4);
-    want = (want + 255) & ~size_t(255);
-    if (hipMalloc(&b.p, want) != hipSuccess) {
-        (void)hipGetLastError();
-        b.p = nullptr;
-        return set_err(EA_ENOMEM, "hipMalloc(%zu) failed", want);
-    }
-    b.bytes = want;
-    return EA_OK;
-}
-
-int check(const ea_mps *h) {
-    if (!h) return set_err(EA_EINVAL, "null handle");
-    if (h->poisoned) return set_err(EA_EHIP, "handle poisoned by an earlier HIP error");
-    return EA_OK;
-}
-
-bool finite_cplx(const double *p, size_t n) {
-    for (size_t i = 0; i < 2 * n; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
-}
-
-// ||A^H A - I||_max for a k x k complex matrix given as interleaved doubles.
-bool is_unitary(const double *a, int k) {
-    for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) {
-            double re = 0, im = 0;
-            for (int r = 0; r < k; ++r) {
-                double ar = a[2 * (r * k + i)], ai = -a[2 * (r * k + i) + 1];
-                double br = a[2 * (r * k + j)], bi = a[2 * (r * k + j) + 1];
-                re += ar * br - ai * bi;
-                im += ar * bi + ai * br;
-            }
-            if (std::fabs(re - (i == j ? 1.0 : 0.0)) > 1e-12 || std::fabs(im) > 1e-12) return false;
-        }
-    return true;
-}
-
-// Copy n complex doubles into the pinned staging ring, converted to T, and
-// enqueue the upload on the handle's stream.  Slots are reused only after a
-// stream synchronisation, so earlier kernels never see later operands.
-template <typename T>
-int stage(ea_mps *h, const double *src, size_t n, void **dev) {
-    const size_t bytes = n * 2 * sizeof(T);
-    size_t need = (bytes + 255) & ~size_t(255);
-    if (need > h->stage_cap) return set_err(EA_ETOOBIG, "operand too large for staging");
-    if (h->stage_off + need > h->stage_cap) {
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        h->stage_off = 0;
-    }
-    T *dst = reinterpret_cast<T *>(h->stage_host + h->stage_off);
-    for (size_t i = 0; i < 2 * n; ++i) dst[i] = (T)src[i];
-    char *d = (char *)h->stage_dev.p + h->stage_off;
-    HIPCHK(h, hipMemcpyAsync(d, dst, bytes, hipMemcpyHostToDevice, h->stream));
-    h->stage_off += need;
-    *dev = d;
-    return EA_OK;
-}
-
-double schedule_target(const ea_mps *h) {
-    if (!h->has_sched) return 1.0;
-    const double n = (double)h->n_total, g = (double)h->g;
-    double ft;
-    if (h->strategy == EA_NAIVE) {
-        ft = std::pow(h->f_min, 1.0 / n);
-    } else if (h->strategy == EA_GLOBAL) {
-        double left = n - g;
-        ft = left <= 0 ? 1.0 : std::exp((std::log(h->f_min) - h->lnP) / left);
-    } else {
-        ft = std::exp(std::log(h->f_min) * (g + 1) / n - h->lnP);
-    }
-    return std::min(1.0, std::max(ft, 1e-300));
-}
-
-template <typename T>
-double default_tol(int m) {
-    return (double)m * (sizeof(T) == 8 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
-}
-
-// One-sided Jacobi on W (m x n, column-major, m >= n), V <- accumulated
-// rotations.  Writes (sweeps, converged) to ints[0..1] on the device.
-template <typename T>
-int svd_core(ea_mps *h, int m, int n) {
-    int *sweeps_dev = (int *)h->ints.p;
-    int *counter = sweeps_dev + 2;
-    const double tol = h->tol > 0 ? h->tol : default_tol<T>(m);
-    const double c = (double)h->csz;
-    {
-        ProfScope ps(h, EA_K_OTHER, 0.0, c * n * (double)n);
-        launch_eye<T>(h->V.p, n, h->stream);
-    }
-    if (n <= 64) {
-        ProfScope ps(h, EA_K_JSMALL, 0.0, 2.0 * c * (m + n) * (double)n);
-        launch_jacobi_single<T>(h->W.p, m, h->V.p, n, tol, h->inner_max, h->max_sweeps,
-                                sweeps_dev, h->stream);
-        LAUNCHCHK(h);
-        return EA_OK;
-    }
-    const bool three = h->jkernel == 0;
-    int w = h->block > 0 ? h->block : (three ? 16 : (n <= 256 ? 8 : 16));
-    if (2 * w > 64) w = 32;
-    const int ncmax = 2 * w <= 16 ? 16 : (2 * w <= 32 ? 32 : 64);
-    int nb = (n + w - 1) / w;
-    nb += nb & 1;
-    if (three) {
-        TRY(ensure(h, h->jpart, h->csz * jacobi_round3_partial_elems(m, n, w)));
-        TRY(ensure(h, h->jmat, h->csz * jacobi_round3_j_elems(n, w)));
-        TRY(ensure(h, h->jflag, sizeof(int) * (nb / 2 + 1)));
-    }
-    int sweeps = 0, conv = 0;
-    for (int sw = 0; sw < h->max_sweeps; ++sw) {
-        launch_fill_int(counter, 1, 0, h->stream);
-        for (int rnd = 0; rnd < nb - 1; ++rnd) {
-            // algorithmic work of one round: every column block pair forms its
-            // Hermitian Gram matrix (4 m nc^2 flops) and rotates its nc columns of W
-            // and V (8 (m + n) nc^2 flops)
-            double fl2 = 0.0;
-            for (int p = 0; p < nb / 2; ++p) {
-                const int a = p == 0 ? 0 : (p - 1 + rnd) % (nb - 1) + 1;
-                const int bq = nb - 1 - p;
-                const int b = bq == 0 ? 0 : (bq - 1 + rnd) % (nb - 1) + 1;
-                const int nc = std::max(0, std::min(w, n - a * w)) + std::max(0, std::min(w, n - b * w));
-                fl2 += (double)nc * nc;
-            }
-            if (three) {
-                {
-                    ProfScope ps(h, EA_K_JGRAM, 4.0 * m * fl2, c * m * (double)n);
-                    launch_jacobi_part<T>(0, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          h->rot_threads, h->stream);
-                }
-                {
-                    ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * 64.0 * 64.0);
-                    launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          h->rot_threads, h->stream);
-                }
-                {
-                    ProfScope ps(h, EA_K_JAPPLY, 8.0 * (m + n) * fl2, 2.0 * c * (m + n) * (double)n);
-                    launch_jacobi_part<T>(2, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          h->rot_threads, h->stream);
-                }
-            } else {
-                ProfScope ps(h, EA_K_JFUSED, (4.0 * m + 8.0 * (m + n)) * fl2,
-                             2.0 * c * (m + n) * (double)n);
-                launch_jacobi_round<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, 6, ncmax, counter,
-                                       h->stream);
-            }
-        }
-        LAUNCHCHK(h);
-        HIPCHK(h, hipMemcpyAsync(h->int_host, counter, sizeof(int), hipMemcpyDeviceToHost,
-                                 h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        ++sweeps;
-        // algorithmic work of the rotations of this sweep: each rotation updates
-        // two rows of the Hermitian Gram matrix and two columns of J (48 nc flops)
-        if (h->prof_on && three) h->prof_flops[EA_K_JROT] += 48.0 * 2 * w * (double)h->int_host[0];
-        if (h->int_host[0] == 0) {
-            conv = 1;
-            break;
-        }
-    }
-    launch_fill_int(sweeps_dev, 1, sweeps, h->stream);
-    launch_fill_int(sweeps_dev + 1, 1, conv, h->stream);
-    return EA_OK;
-}
-
-// Factor matrix X (rows x cols, currently in W as column-major after the
-// caller's copy/contraction) and read back the decision record.
-template <typename T>
-int factor_and_decide(ea_mps *h, int mw, int nw, double f_t, int mode, int forced_k) {
-    TRY(ensure(h, h->s_raw, sizeof(double) * nw));
-    TRY(ensure(h, h->s_sorted, sizeof(double) * nw));
-    TRY(ensure(h, h->perm, sizeof(int) * nw));
-    TRY(svd_core<T>(h, mw, nw));
-    {
-        ProfScope ps(h, EA_K_NORMS, 4.0 * mw * (double)nw, (double)h->csz * mw * (double)nw);
-        launch_colnorms<T>(h->W.p, mw, nw, (double *)h->s_raw.p, h->stream);
-    }
-    {
-        ProfScope ps(h, EA_K_TRUNC, (double)nw, 24.0 * nw);
-        launch_sort_trunc((const double *)h->s_raw.p, nw, f_t, h->chi_max, h->tau, mode,
-                          forced_k, (const int *)h->ints.p, (int *)h->perm.p,
-                          (double *)h->s_sorted.p, (ea_dev_rec *)h->rec.p, h->stream);
-    }
-    LAUNCHCHK(h);
-    HIPCHK(h, hipMemcpyAsync(h->rec_host, h->rec.p, sizeof(ea_dev_rec), hipMemcpyDeviceToHost,
-                             h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    prof_harvest(h);
-    return EA_OK;
-}
-
-template <typename T>
-void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int es, int ec,
-            int transposed, void *out) {
-    ProfScope ps(h, EA_K_GATHER, 0.0, 2.0 * (double)h->csz * k * (double)X);
-    launch_gather<T>(src, ld, (const int *)h->perm.p, (const double *)h->s_sorted.p,
-                     (const ea_dev_rec *)h->rec.p, k, X, conj_src, es, ec, transposed, out,
-                     h->stream);
-}
-
-// Move the orthogonality centre one site right: SVD of A_c as
-// (chi_l d) x chi_r; A_c <- U, A_{c+1} <- (S V^H) A_{c+1}.
-template <typename T>
-int move_right(ea_mps *h) {
-    const int c = h->center, d = h->d;
-    const int M = h->bond[c] * d, N = h->bond[c + 1];
-    const int orient = M >= N ? 0 : 1, mw = std::max(M, N), nw = std::min(M, N);
-    if (nw > EA_SORT_MAX) return set_err(EA_ETOOBIG, "bond too large for centre move");
-    TRY(ensure(h, h->W, h->csz * (size_t)mw * nw));
-    TRY(ensure(h, h->V, h->csz * (size_t)nw * nw));
-    {
-        ProfScope ps(h, EA_K_OTHER, 0.0, 2.0 * (double)h->csz * M * (double)N);
-        launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, orient, h->stream);
-    }
-    TRY(factor_and_decide<T>(h, mw, nw, 1.0, 1, 0));
-    const int k = h->rec_host->k;
-    if (!(h->rec_host->s0 > 0.0)) return set_err(EA_EINVAL, "zero site tensor");
-    const int chi2 = h->bond[c + 2];
-    TRY(ensure(h, h->site[c], h->csz * (size_t)M * k));
-    TRY(ensure(h, h->X, h->csz * (size_t)k * N));
-    if (orient == 0) {
-        gather<T>(h, h->W.p, M, k, M, 0, -1, 0, 1, h->site[c].p);
-        gather<T>(h, h->V.p, N, k, N, 1, 1, 0, 0, h->X.p);
-    } else {
-        gather<T>(h, h->V.p, M, k, M, 0, 0, 0, 1, h->site[c].p);
-        gather<T>(h, h->W.p, N, k, N, 1, 0, 0, 0, h->X.p);
-    }
-    TRY(ensure(h, h->spare, h->csz * (size_t)k * d * chi2));
-    {
-        ProfScope ps(h, EA_K_GEMM, 8.0 * k * (double)(d * chi2) * N,
-                     (double)h->csz * ((double)k * N + (double)N * d * chi2 + (double)k * d * chi2));
-        launch_gemm<T>(h->X.p, h->site[c + 1].p, h->spare.p, k, d * chi2, N, N, d * chi2,
-                       d * chi2, h->stream);
-    }
-    LAUNCHCHK(h);
-    std::swap(h->site[c + 1], h->spare);
-    h->bond[c + 1] = k;
-    h->center = c + 1;
-    return EA_OK;
-}
-
-// Move the centre one site left: SVD of A_c as chi_l x (d chi_r);
-// A_c <- V^H, A_{c-1} <- A_{c-1} (U S).
-template <typename T>
-int move_left(ea_mps *h) {
-    const int c = h->center, d = h->d;
-    const int M = h->bond[c], N = d * h->bond[c + 1];
-    const int orient = M >= N ? 0 : 1, mw = std::max(M, N), nw = std::min(M, N);
-    if (nw > EA_SORT_MAX) return set_err(EA_ETOOBIG, "bond too large for centre move");
-    TRY(ensure(h, h->W, h->csz * (size_t)mw * nw));
-    TRY(ensure(h, h->V, h->csz * (size_t)nw * nw));
-    {
-        ProfScope ps(h, EA_K_OTHER, 0.0, 2.0 * (double)h->csz * M * (double)N);
-        launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, orient, h->stream);
-    }
-    TRY(factor_and_decide<T>(h, mw, nw, 1.0, 1, 0));
-    const int k = h->rec_host->k;
-    if (!(h->rec_host->s0 > 0.0)) return set_err(EA_EINVAL, "zero site tensor");
-    const int rowsP = h->bond[c - 1] * d;
-    TRY(ensure(h, h->site[c], h->csz * (size_t)k * N));
-    TRY(ensure(h, h->X, h->csz * (size_t)M * k));
-    if (orient == 0) {
-        gather<T>(h, h->V.p, N, k, N, 1, 0, 0, 0, h->site[c].p);
-        gather<T>(h, h->W.p, M, k, M, 0, 0, 0, 1, h->X.p);
-    } else {
-        gather<T>(h, h->W.p, N, k, N, 1, -1, 0, 0, h->site[c].p);
-        gather<T>(h, h->V.p, M, k, M, 0, 1, 0, 1, h->X.p);
-    }
-    TRY(ensure(h, h->spare, h->csz * (size_t)rowsP * k));
-    {
-        ProfScope ps(h, EA_K_GEMM, 8.0 * rowsP * (double)k * M,
-                     (double)h->csz * ((double)rowsP * M + (double)M * k + (double)rowsP * k));
-        launch_gemm<T>(h->site[c - 1].p, h->X.p, h->spare.p, rowsP, k, M, M, k, k, h->stream);
-    }
-    LAUNCHCHK(h);
-    std::swap(h->site[c - 1], h->spare);
-    h->bond[c] = k;
-    h->center = c - 1;
-    return EA_OK;
-}
-
-template <typename T>
-int move_center(ea_mps *h, int j) {
-    while (h->center < j) {
-        ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
-        TRY(move_right<T>(h));
-    }
-    while (h->center > j) {
-        ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
-        TRY(move_left<T>(h));
-    }
-    return EA_OK;
-}
-
-// Two-site update on (i, i+1); dir = +1: centre ends on i+1, -1: on i.
-template <typename T>
-int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, double *f_out,
-                  int forced_k) {
-    if (h->center < i) TRY(move_center<T>(h, i));
-    if (h->center > i + 1) TRY(move_center<T>(h, i + 1));
-    double f_t = budget >= 0 ? budget : schedule_target(h);
-    f_t = std::min(1.0, std::max(f_t, 1e-300));
-    const int d = h->d, chiL = h->bond[i], chiM = h->bond[i + 1], chiR = h->bond[i + 2];
-    const int M = d * chiL, N = d * chiR;
-    const int orient = M >= N ? 0 : 1, mw = std::max(M, N), nw = std::min(M, N);
-    if (nw > EA_SORT_MAX) return set_err(EA_ETOOBIG, "two-site matrix too large (%d)", nw);
-    TRY(ensure(h, h->W, h->csz * (size_t)mw * nw));
-    TRY(ensure(h, h->V, h->csz * (size_t)nw * nw));
-    void *G = nullptr;
-    TRY(stage<T>(h, op, (size_t)d * d * d * d, &G));
-    {
-        const double dd = d;
-        ProfScope ps(h, EA_K_THETA,
-                     8.0 * dd * dd * chiL * (double)chiM * chiR + 8.0 * dd * dd * dd * dd * chiL * (double)chiR,
-                     (double)h->csz * (dd * chiL * chiM + dd * chiM * (double)chiR +
-                                       dd * dd * chiL * (double)chiR + dd * dd * dd * dd));
-        launch_theta<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d, orient,
-                        h->stream);
-    }
-    LAUNCHCHK(h);
-    TRY(factor_and_decide<T>(h, mw, nw, f_t, 0, forced_k));
-    const ea_dev_rec rec = *h->rec_host;
-    const int k = rec.k;
-    if (!(rec.s0 > 0.0) || !std::isfinite(rec.total))
-        return set_err(EA_EINVAL, "the operator annihilates the state (all singular values 0)");
-    TRY(ensure(h, h->site[i], h->csz * (size_t)M * k));
-    TRY(ensure(h, h->site[i + 1], h->csz * (size_t)k * N));
-    const bool right = dir > 0;
-    if (orient == 0) {
-        gather<T>(h, h->W.p, M, k, M, 0, right ? -1 : 0, right ? 0 : 1, 1, h->site[i].p);
-        gather<T>(h, h->V.p, N, k, N, 1, right ? 1 : 0, right ? 1 : 0, 0, h->site[i + 1].p);
-    } else {
-        gather<T>(h, h->V.p, M, k, M, 0, right ? 0 : 1, right ? 0 : 1, 1, h->site[i].p);
-        gather<T>(h, h->W.p, N, k, N, 1, right ? 0 : -1, right ? 1 : 0, 0, h->site[i + 1].p);
-    }
-    LAUNCHCHK(h);
-    h->bond[i + 1] = k;
-    h->center = right ? i + 1 : i;
-    h->lnP += rec.lnf;
-    if (h->kind == EA_MIXED && rec.kept2 > 0) h->lnS += 0.5 * std::log(rec.kept2);
-    ea_gate_record r;
-    r.gate = h->g;
-    r.site = i;
-    r.chi_l = chiL;
-    r.chi_m = chiM;
-    r.chi_r = chiR;
-    r.k = k;
-    r.k_f = rec.k_f;
-    r.sweeps = rec.sweeps;
-    r.capped = rec.capped;
-    r.f_t = f_t;
-    r.f = rec.f;
-    r.total = rec.total;
-    r.lnP = h->lnP;
-    h->log.push_back(r);
-    h->g += 1;
-    if (f_out) *f_out = rec.f;
-    if (rec.capped) return set_err(EA_WARN_CAPPED, "chi_max bound at gate %ld", (long)r.gate);
-    if (!rec.converged) return set_err(EA_WARN_NOCONV, "Jacobi did not converge");
-    return EA_OK;
-}
-
-template <typename T>
-int apply_1q_impl(ea_mps *h, int site, const double *op) {
-    if (!is_unitary(op, h->d)) TRY(move_center<T>(h, site));
-    void *g = nullptr;
-    TRY(stage<T>(h, op, (size_t)h->d * h->d, &g));
-    launch_apply1<T>(h->site[site].p, h->site[site].p, g, h->bond[site], h->d, h->bond[site + 1],
-                     h->stream);
-    LAUNCHCHK(h);
-    return EA_OK;
-}
-
-// <O> for a pure state at the centre (Eq. 6).
-template <typename T>
-int expect_pure(ea_mps *h, int site, int width, const double *op, double *res3) {
-    TRY(move_center<T>(h, site));
-    const int d = h->d;
-    double *dev3 = (double *)h->out3.p;
-    double *partial = (double *)h->partial.p;
-    int nblk;
-    if (width == 1) {
-        const size_t len = (size_t)h->bond[site] * d * h->bond[site + 1];
-        TRY(ensure(h, h->X, h->csz * len));
-        void *g = nullptr;
-        TRY(stage<T>(h, op, (size_t)d * d, &g));
-        launch_apply1<T>(h->site[site].p, h->X.p, g, h->bond[site], d, h->bond[site + 1],
-                         h->stream);
-        nblk = launch_cdot<T>(h->site[site].p, h->X.p, len, partial, 1024, h->stream);
-    } else {
-        const int chiL = h->bond[site], chiM = h->bond[site + 1], chiR = h->bond[site + 2];
-        const size_t len = (size_t)d * chiL * d * chiR;
-        TRY(ensure(h, h->X, h->csz * len));
-        TRY(ensure(h, h->X2, h->csz * len));
-        double eye[32] = {0};
-        for (int a = 0; a < 4; ++a) eye[2 * (a * 4 + a)] = 1.0;
-        void *gi = nullptr, *go = nullptr;
-        TRY(stage<T>(h, eye, 16, &gi));
-        TRY(stage<T>(h, op, 16, &go));
-        launch_theta<T>(h->site[site].p, h->site[site + 1].p, gi, h->X.p, chiL, chiM, chiR, d, 0,
-                        h->stream);
-        launch_theta<T>(h->site[site].p, h->site[site + 1].p, go, h->X2.p, chiL, chiM, chiR, d, 0,
-                        h->stream);
-        nblk = launch_cdot<T>(h->X.p, h->X2.p, len, partial, 1024, h->stream);
-    }
-    launch_cdot_final(partial, nblk, dev3, h->stream);
-    LAUNCHCHK(h);
-    HIPCHK(h, hipMemcpyAsync(res3, dev3, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    return EA_OK;
-}
-
-// All terms of a mixed state: Tr(rho O) / Tr(rho) with left/right transfer
-// vectors built once (identity weights vec(I) = [1, 0, 0, 1]).
-template <typename T>
-int expect_mixed(ea_mps *h, int n_terms, const int *sites, const int *widths, const double *ops,
-                 double *out) {
-    const int n = h->n, d = h->d;
-    std::vector<size_t> offL(n + 1), offR(n + 1);
-    size_t tot = 0;
-    for (int j = 0; j <= n; ++j) {
-        offL[j] = tot;
-        tot += h->bond[j];
-    }
-    for (int j = 0; j <= n; ++j) {
-        offR[j] = tot;
-        tot += h->bond[j];
-    }
-    const size_t term_off = tot;
-    tot += (size_t)n_terms + 1;  // terms, then Tr(rho)
-    int maxchi = *std::max_element(h->bond.begin(), h->bond.end());
-    TRY(ensure(h, h->envb, h->csz * tot));
-    TRY(ensure(h, h->tmp, h->csz * (size_t)d * maxchi + 64));
-    TRY(ensure(h, h->X, h->csz * (size_t)maxchi + 64));
-    char *E = (char *)h->envb.p;
-    auto at = [&](size_t off) { return (void *)(E + off * h->csz); };
-    const double one[2] = {1.0, 0.0};
-    double vid[8] = {1, 0, 0, 0, 0, 0, 1, 0};
-    void *d_one = nullptr, *d_vid = nullptr;
-    TRY(stage<T>(h, one, 1, &d_one));
-    TRY(stage<T>(h, vid, 4, &d_vid));
-    HIPCHK(h, hipMemcpyAsync(at(offL[0]), d_one, 2 * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(at(offR[n]), d_one, 2 * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
-    for (int j = 0; j < n; ++j)
-        launch_env_left<T>(at(offL[j]), h->site[j].p, d_vid, at(offL[j + 1]), h->bond[j], d,
-                           h->bond[j + 1], h->stream);
-    for (int j = n - 1; j >= 0; --j)
-        launch_env_right<T>(h->site[j].p, d_vid, at(offR[j + 1]), at(offR[j]), h->bond[j], d,
-                            h->bond[j + 1], h->stream);
-    LAUNCHCHK(h);
-    size_t opoff = 0;
-    for (int t = 0; t < n_terms; ++t) {
-        const int s = sites[t], w = widths[t];
-        const double *o = ops + 2 * opoff;
-        opoff += w == 1 ? 4 : 16;
-        void *e_out = h->X.p;
-        if (w == 1) {
-            double wg[8];  // weight at p = 2 s + s' is O[s', s]
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b) {
-                    const int p = 2 * a + b;
-                    wg[2 * p] = o[2 * (b * 2 + a)];
-                    wg[2 * p + 1] = o[2 * (b * 2 + a) + 1];
-                }
-            void *dw = nullptr;
-            TRY(stage<T>(h, wg, 4, &dw));
-            launch_env_left<T>(at(offL[s]), h->site[s].p, dw, e_out, h->bond[s], d,
-                               h->bond[s + 1], h->stream);
-        } else {
-            double w2[32];  // W2[p1, p2] = O[(s1' s2'), (s1 s2)]
-            for (int s1 = 0; s1 < 2; ++s1)
-                for (int s1p = 0; s1p < 2; ++s1p)
-                    for (int s2 = 0; s2 < 2; ++s2)
-                        for (int s2p = 0; s2p < 2; ++s2p) {
-                            const int p1 = 2 * s1 + s1p, p2 = 2 * s2 + s2p;
-                            const int src = (2 * s1p + s2p) * 4 + (2 * s1 + s2);
-                            w2[2 * (p1 * 4 + p2)] = o[2 * src];
-                            w2[2 * (p1 * 4 + p2) + 1] = o[2 * src + 1];
-                        }
-            void *dw = nullptr;
-            TRY(stage<T>(h, w2, 16, &dw));
-            launch_env_left2<T>(at(offL[s]), h->site[s].p, h->site[s + 1].p, dw, h->tmp.p, e_out,
-                                h->bond[s], d, h->bond[s + 1], h->bond[s + 2], h->stream);
-        }
-        // plain dot with the right transfer vector: treat it as a chi x 1 x 1 tensor
-        const int chi = h->bond[s + w];
-        launch_env_left<T>(e_out, at(offR[s + w]), d_one, at(term_off + t), chi, 1, 1, h->stream);
-    }
-    LAUNCHCHK(h);
-    // results: Tr(rho) = L_N[0]; terms
-    const size_t nres = n_terms + 1;
-    TRY(ensure(h, h->c128, sizeof(double) * 2 * nres));
-    HIPCHK(h, hipMemcpyAsync(at(term_off + n_terms), at(offL[n]), h->csz, hipMemcpyDeviceToDevice,
-                             h->stream));
-    launch_to_c128<T>(at(term_off), (double *)h->c128.p, nres, h->stream);
-    std::vector<double> host(2 * nres);
-    HIPCHK(h, hipMemcpyAsync(host.data(), h->c128.p, sizeof(double) * 2 * nres,
-                             hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    const double tr = host[2 * n_terms], ti = host[2 * n_terms + 1];
-    const double den = tr * tr + ti * ti;
-    for (int t = 0; t < n_terms; ++t) {
-        const double a = host[2 * t], b = host[2 * t + 1];
-        out[2 * t] = (a * tr + b * ti) / den;
-        out[2 * t + 1] = (b * tr - a * ti) / den;
-    }
-    return EA_OK;
-}
-
-template <typename T>
-int to_vector_impl(ea_mps *h, double *out, size_t out_len) {
-    const int n = h->n, d = h->d;
-    size_t total = 1;
-    for (int j = 0; j < n; ++j) total *= (size_t)d;
-    if (out_len < total) return set_err(EA_ETOOBIG, "output needs %zu complex entries", total);
-    // chain contraction: cur (rows x chi_j) * A_j (chi_j x d chi_{j+1})
-    size_t maxsz = total, rows_j = 1;
-    for (int j = 0; j < n; ++j) {
-        rows_j *= (size_t)d;
-        maxsz = std::max(maxsz, rows_j * (size_t)h->bond[j + 1]);
-    }
-    TRY(ensure(h, h->X, h->csz * maxsz));
-    TRY(ensure(h, h->X2, h->csz * maxsz));
-    size_t rows = d;
-    HIPCHK(h, hipMemcpyAsync(h->X.p, h->site[0].p, h->csz * d * h->bond[1],
-                             hipMemcpyDeviceToDevice, h->stream));
-    void *cur = h->X.p, *nxt = h->X2.p;
-    for (int j = 1; j < n; ++j) {
-        const int cl = h->bond[j], cr = h->bond[j + 1];
-        launch_gemm<T>(cur, h->site[j].p, nxt, (int)rows, d * cr, cl, cl, d * cr, d * cr,
-                       h->stream);
-        rows *= d;
-        std::swap(cur, nxt);
-    }
-    LAUNCHCHK(h);
-    void *res = cur;
-    if (h->kind == EA_MIXED) {
-        // trace = sum over rows of rho's diagonal: use the transfer vectors
-        launch_vec_to_rho<T>(cur, nxt, n, h->stream);
-        res = nxt;
-        const size_t dim = (size_t)1 << n;
-        // Tr(rho) from the diagonal: diagonal entries have stride dim+1
-        TRY(ensure(h, h->tmp, h->csz * dim));
-        // gather the diagonal with a strided copy
-        HIPCHK(h, hipMemcpy2DAsync(h->tmp.p, h->csz, res, h->csz * (dim + 1), h->csz, dim,
-                                   hipMemcpyDeviceToDevice, h->stream));
-        TRY(ensure(h, h->envb, h->csz * dim));
-        std::vector<double> ones(2 * dim, 0.0);
-        for (size_t i = 0; i < dim; ++i) ones[2 * i] = 1.0;
-        void *d1 = nullptr;
-        if (dim * 2 * sizeof(T) * 2 <= h->stage_cap) {
-            TRY(stage<T>(h, ones.data(), dim, &d1));
-        } else {
-            return set_err(EA_ETOOBIG, "density matrix too large");
-        }
-        int nb = launch_cdot<T>(d1, h->tmp.p, dim, (double *)h->partial.p, 1024, h->stream);
-        launch_cdot_final((double *)h->partial.p, nb, (double *)h->out3.p, h->stream);
-        double tr[3];
-        HIPCHK(h, hipMemcpyAsync(tr, h->out3.p, 3 * sizeof(double), hipMemcpyDeviceToHost,
-                                 h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        const double den = tr[0] * tr[0] + tr[1] * tr[1];
-        launch_scale<T>(res, total, tr[0] / den, -tr[1] / den, h->stream);
-    }
-    if (h->f64) {
-        HIPCHK(h, hipMemcpyAsync(out, res, 16 * total, hipMemcpyDeviceToHost, h->stream));
-    } else {
-        TRY(ensure(h, h->c128, 16 * total));
-        launch_to_c128<T>(res, (double *)h->c128.p, total, h->stream);
-        HIPCHK(h, hipMemcpyAsync(out, h->c128.p, 16 * total, hipMemcpyDeviceToHost, h->stream));
-    }
-    LAUNCHCHK(h);
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    return EA_OK;
-}
-
-template <typename T>
-int load_impl(ea_mps *h, const int *dims, const double *data, int center) {
-    const int n = h->n, d = h->d;
-    size_t off = 0;
-    for (int j = 0; j < n; ++j) {
-        const size_t sz = (size_t)dims[j] * d * dims[j + 1];
-        TRY(ensure(h, h->site[j], h->csz * sz));
-        TRY(ensure(h, h->c128, 16 * sz));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipMemcpy(h->c128.p, data + 2 * off, 16 * sz, hipMemcpyHostToDevice));
-        launch_from_c128<T>((const double *)h->c128.p, h->site[j].p, sz, h->stream);
-        LAUNCHCHK(h);
-        off += sz;
-    }
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int j = 0; j <= n; ++j) h->bond[j] = dims[j];
-    h->center = center;
-    return EA_OK;
-}
-
-template <typename T>
-int get_site_impl(ea_mps *h, int site, double *out) {
-    const size_t sz = (size_t)h->bond[site] * h->d * h->bond[site + 1];
-    TRY(ensure(h, h->c128, 16 * sz));
-    launch_to_c128<T>(h->site[site].p, (double *)h->c128.p, sz, h->stream);
-    LAUNCHCHK(h);
-    HIPCHK(h, hipMemcpyAsync(out, h->c128.p, 16 * sz, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    return EA_OK;
-}
-
-void free_buf(DevBuf &b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-}
-
-}  // namespace
+using namespace ea;
 
 // ============================================================================
 // C ABI

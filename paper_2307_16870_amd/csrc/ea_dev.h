@@ -9,7 +9,7 @@ struct alignas(2 * sizeof(T)) cx {
 };
 
 template <typename T>
-__device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+__host__ __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
 template <typename T>
 __device__ __forceinline__ cx<T> zero_cx() { return mk<T>(T(0), T(0)); }
 template <typename T>

@@ -124,3 +124,36 @@ void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb,
                         int *rot_counter, int rot_threads, hipStream_t s);
 size_t jacobi_round3_partial_elems(int m, int n, int w);
 size_t jacobi_round3_j_elems(int n, int w);
+
+// ---- reverse pass (k_adjoint.hip) ------------------------------------------
+// C (M x N) = alpha op(A) op(B) + beta C, row-major; op 1 = conjugate transpose
+// (the operand is then stored transposed).
+template <typename T>
+void launch_gemm_ex(int opA, int opB, int M, int N, int K, double ar, double ai, const void *A,
+                    int lda, const void *B, int ldb, double br, double bi, void *C, int ldc,
+                    hipStream_t s);
+template <typename T>
+void launch_axpby(size_t n, double ar, double ai, const void *X, double br, double bi, void *Y,
+                  hipStream_t s);
+// Y[j][i] = cst * scale_i^power * conj(X[i][j]) for i < rows_used, else 0.
+template <typename T>
+void launch_conjT_scaled(int rows, int rows_used, int cols, const void *X, int ldx,
+                         const double *scale, int power, double cst, void *Y, int ldy,
+                         hipStream_t s);
+template <typename T>
+void launch_scale_cols(int rows, int cols, void *X, int ld, const double *scale, int power,
+                       hipStream_t s);
+template <typename T>
+void launch_rowdot_re(int k, int n, const void *X, int ldx, const void *Y, int ldy, double *out,
+                      hipStream_t s);
+template <typename T>
+void launch_coldot_re(int rows, int cols, const void *A, const void *B, int ld, double *out,
+                      hipStream_t s);
+void launch_sbar_renorm(int k, int r, const double *stbar, const double *s, double sig,
+                        double *sbar, hipStream_t st);
+template <typename T>
+void launch_svdvjp_P(int r, const void *J, const void *K, const double *s, const double *sbar,
+                     double eta, void *P, hipStream_t st);
+template <typename T>
+void launch_gbar_grad(const void *Ab, const void *A, int chiL, int chiR, double *partial,
+                      const double *dg, double *grad, int param, hipStream_t s);

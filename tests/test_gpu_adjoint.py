@@ -1,0 +1,67 @@
+"""GPU adjoint (reverse pass in the library) against the FP64 adjoint oracle,
+which is itself pinned by central differences and the parameter-shift rule."""
+import numpy as np
+import pytest
+
+import circuits as C
+from oracle.adjoint import hea_energy_and_grad
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2307_16870_amd")
+
+
+@pytest.mark.parametrize("n,L,f_min", [(6, 3, 0.999), (7, 4, 0.99), (5, 3, 1.0)])
+def test_energy_grad_small_vs_oracle(n, L, f_min):
+    print("case: adjoint small", n, L, f_min, flush=True)
+    angles = C.hea_angles(n, L, seed=7)
+    terms = C.hea_hamiltonian(n)
+    Eo, go, ranks, lnPo = hea_energy_and_grad(angles, terms, f_min=None if f_min >= 1 else f_min)
+    with P.EAState(n, "pure", "c128") as st:
+        E, g, lnP = P.mps_energy_grad(st.h, P.hea_dops(n, L), angles, terms, f_min=f_min)
+        ks = [r["k"] for r in st.gate_log()]
+    assert ks == ranks
+    assert abs(E - Eo) < 1e-10
+    assert abs(lnP - lnPo) < 1e-10
+    np.testing.assert_allclose(g, go.reshape(-1), atol=1e-10)
+
+
+def test_energy_grad_hea32_vs_oracle():
+    """The 32-qubit, 10-layer hardware-efficient ansatz, F_min = 0.999:
+    energy and all 640 angle derivatives within 1e-10 of the FP64 oracle."""
+    print("case: adjoint hea32", flush=True)
+    angles = C.hea_angles(32, 10, seed=5)
+    terms = C.hea_hamiltonian(32)
+    Eo, go, ranks, lnPo = hea_energy_and_grad(angles, terms, f_min=0.999)
+    with P.EAState(32, "pure", "c128") as st:
+        E, g, lnP = P.mps_energy_grad(st.h, P.hea_dops(32, 10), angles, terms, f_min=0.999)
+        ks = [r["k"] for r in st.gate_log()]
+    assert ks == ranks
+    assert lnPo < 0 and abs(lnP - lnPo) < 1e-10
+    assert abs(E - Eo) < 1e-10
+    np.testing.assert_allclose(g, go.reshape(-1), atol=1e-10)
+
+
+def test_energy_grad_fp32_tolerance():
+    print("case: adjoint fp32", flush=True)
+    angles = C.hea_angles(10, 4, seed=3)
+    terms = C.hea_hamiltonian(10)
+    Eo, go, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999)
+    with P.EAState(10, "pure", "c64") as st:
+        E, g, _ = P.mps_energy_grad(st.h, P.hea_dops(10, 4), angles, terms, f_min=0.999)
+    assert abs(E - Eo) < 1e-4
+    assert np.abs(g - go.reshape(-1)).max() < 1e-3
+
+
+def test_autograd_function():
+    print("case: autograd", flush=True)
+    torch = pytest.importorskip("torch")
+    from paper_2307_16870_amd.autograd import ea_energy
+    angles = C.hea_angles(6, 3, seed=9)
+    terms = C.hea_hamiltonian(6)
+    Eo, go, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999)
+    p = torch.tensor(angles, dtype=torch.float64, requires_grad=True)
+    with P.EAState(6, "pure", "c128") as st:
+        E = ea_energy(p, st, P.hea_dops(6, 3), terms, f_min=0.999)
+        (2.0 * E).backward()
+    assert abs(E.item() - Eo) < 1e-10
+    np.testing.assert_allclose(p.grad.numpy(), 2.0 * go, atol=1e-10)
