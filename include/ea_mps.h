@@ -87,8 +87,15 @@ enum ea_option {
     EA_OPT_INNER_SWEEPS = 5, /* rotation sweeps over a block pair's Gram per round (default 1) */
     EA_OPT_JACOBI_KERNEL = 6,/* 0: Gram / rotations / apply as three kernels (MFMA);
                                 1: one fused kernel per round (vector ALU) */
-    EA_OPT_ROT_THREADS = 7   /* threads of the per-pair rotation kernel: 64, 128, 256,
+    EA_OPT_ROT_THREADS = 7,  /* threads of the per-pair rotation kernel: 64, 128, 256,
                                 512 (default) or 1024 */
+    EA_OPT_REORTH = 8,       /* FP32 precisions: 1 (default) re-orthogonalises every
+                                isometric factor in FP64 after its factorisation */
+    EA_OPT_JACOBI_ORDER = 9  /* three-kernel Jacobi: 1 (default) rotates the column pairs
+                                inside a block in the first round of a sweep only, later
+                                rounds rotate only pairs across the two blocks (every pair
+                                once per sweep); 0 rotates all pairs of the block pair in
+                                every round */
 };
 
 /* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */

@@ -99,7 +99,7 @@ void mps_free(ea_mps *h) {
     prof_harvest(h);
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     for (auto &b : h->site) free_buf(b);
-    DevBuf *bufs[] = {&h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
+    DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
                       &h->stage_dev};
     for (DevBuf *b : bufs) free_buf(*b);
@@ -141,6 +141,14 @@ int mps_set_option(ea_mps *h, int option, double value) {
     case EA_OPT_JACOBI_KERNEL:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi kernel must be 0 or 1");
         h->jkernel = (int)value;
+        return EA_OK;
+    case EA_OPT_REORTH:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "reorth must be 0 or 1");
+        h->reorth = value != 0;
+        return EA_OK;
+    case EA_OPT_JACOBI_ORDER:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi order must be 0 or 1");
+        h->jorder = (int)value;
         return EA_OK;
     case EA_OPT_ROT_THREADS:
         if (value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)

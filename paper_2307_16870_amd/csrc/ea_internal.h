@@ -55,7 +55,10 @@ struct ea_mps {
     int strategy = EA_GLOBAL;
     // workspace
     ea::DevBuf jpart, jmat, jflag;
+    ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
+    bool reorth = true;
     int inner_round = 1, jkernel = 0, rot_threads = 512;
+    int jorder = 1;  // 1: pairs inside a column block rotated in a sweep's first round only
     ea::DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
     ea_dev_rec *rec_host = nullptr;
     int *int_host = nullptr;
@@ -271,6 +274,8 @@ int svd_core(ea_mps *h, int m, int n) {
     for (int sw = 0; sw < h->max_sweeps; ++sw) {
         launch_fill_int(counter, 1, 0, h->stream);
         for (int rnd = 0; rnd < nb - 1; ++rnd) {
+            // pairs inside a block are rotated in the sweep's first round only
+            const int inter = (h->jorder == 1 && rnd > 0) ? 1 : 0;
             // algorithmic work of one round: every column block pair forms its
             // Hermitian Gram matrix (4 m nc^2 flops) and rotates its nc columns of W
             // and V (8 (m + n) nc^2 flops)
@@ -286,19 +291,19 @@ int svd_core(ea_mps *h, int m, int n) {
                 {
                     ProfScope ps(h, EA_K_JGRAM, 4.0 * m * fl2, c * m * (double)n);
                     launch_jacobi_part<T>(0, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                          inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
                                           h->rot_threads, h->stream);
                 }
                 {
                     ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * 64.0 * 64.0);
                     launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                          inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
                                           h->rot_threads, h->stream);
                 }
                 {
                     ProfScope ps(h, EA_K_JAPPLY, 8.0 * (m + n) * fl2, 2.0 * c * (m + n) * (double)n);
                     launch_jacobi_part<T>(2, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
-                                          h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
+                                          inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
                                           h->rot_threads, h->stream);
                 }
             } else {
@@ -361,6 +366,51 @@ void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int 
                      h->stream);
 }
 
+// FP64 re-orthogonalisation of the isometric factor written by an FP32
+// factorisation (one Loewdin step).  cols = 1: X (rows x k, row-major) should
+// have orthonormal columns and the neighbour N (k x ncols) absorbs R from the
+// left; cols = 0: X (k x rows) should have orthonormal rows and N (nrows x k)
+// absorbs R from the right.  With G = X^H X (or X X^H) = I + E formed in FP64,
+// X <- X (I - E/2) and N <- (I + E/2) N keep the product to O(E^2).
+template <typename T>
+int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) {
+    if (sizeof(T) == 8 || !h->reorth || k < 1) return EA_OK;
+    const size_t nx = (size_t)rows * k;
+    TRY(ensure(h, h->ro_x64, 16 * nx));
+    TRY(ensure(h, h->ro_g, 16 * (size_t)k * k));
+    TRY(ensure(h, h->ro_y, h->csz * (size_t)k * k));
+    TRY(ensure(h, h->ro_r, h->csz * (size_t)k * k));
+    TRY(ensure(h, h->ro_t, h->csz * std::max(nx, (size_t)k * nother)));
+    ProfScope ps(h, EA_K_OTHER, 8.0 * rows * (double)k * k * 2 + 8.0 * k * (double)k * nother,
+                 (double)h->csz * (3.0 * nx + 2.0 * k * (double)nother));
+    launch_to_c128<T>(X, (double *)h->ro_x64.p, nx, h->stream);
+    if (cols)
+        launch_gemm_ex<double>(1, 0, k, k, rows, 1, 0, h->ro_x64.p, k, h->ro_x64.p, k, 0, 0,
+                               h->ro_g.p, k, h->stream);
+    else
+        launch_gemm_ex<double>(0, 1, k, k, rows, 1, 0, h->ro_x64.p, rows, h->ro_x64.p, rows, 0, 0,
+                               h->ro_g.p, k, h->stream);
+    launch_reorth_factors<T>(k, h->ro_g.p, h->ro_y.p, h->ro_r.p, h->stream);
+    if (cols) {
+        launch_gemm_ex<T>(0, 0, rows, k, k, 1, 0, X, k, h->ro_y.p, k, 0, 0, h->ro_t.p, k, h->stream);
+        HIPCHK(h, hipMemcpyAsync(X, h->ro_t.p, h->csz * nx, hipMemcpyDeviceToDevice, h->stream));
+        launch_gemm_ex<T>(0, 0, k, nother, k, 1, 0, h->ro_r.p, k, N, nother, 0, 0, h->ro_t.p,
+                          nother, h->stream);
+        HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)k * nother,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    } else {
+        launch_gemm_ex<T>(0, 0, k, rows, k, 1, 0, h->ro_y.p, k, X, rows, 0, 0, h->ro_t.p, rows,
+                          h->stream);
+        HIPCHK(h, hipMemcpyAsync(X, h->ro_t.p, h->csz * nx, hipMemcpyDeviceToDevice, h->stream));
+        launch_gemm_ex<T>(0, 0, nother, k, k, 1, 0, N, k, h->ro_r.p, k, 0, 0, h->ro_t.p, k,
+                          h->stream);
+        HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)nother * k,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    }
+    LAUNCHCHK(h);
+    return EA_OK;
+}
+
 // Move the orthogonality centre one site right: SVD of A_c as
 // (chi_l d) x chi_r; A_c <- U, A_{c+1} <- (S V^H) A_{c+1}.
 template <typename T>
@@ -397,6 +447,7 @@ int move_right(ea_mps *h) {
     }
     LAUNCHCHK(h);
     std::swap(h->site[c + 1], h->spare);
+    TRY(reorth<T>(h, true, h->site[c].p, M, k, h->site[c + 1].p, d * chi2));
     h->bond[c + 1] = k;
     h->center = c + 1;
     return EA_OK;
@@ -437,6 +488,7 @@ int move_left(ea_mps *h) {
     }
     LAUNCHCHK(h);
     std::swap(h->site[c - 1], h->spare);
+    TRY(reorth<T>(h, false, h->site[c].p, N, k, h->site[c - 1].p, rowsP));
     h->bond[c] = k;
     h->center = c - 1;
     return EA_OK;
@@ -477,8 +529,12 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
                      8.0 * dd * dd * chiL * (double)chiM * chiR + 8.0 * dd * dd * dd * dd * chiL * (double)chiR,
                      (double)h->csz * (dd * chiL * chiM + dd * chiM * (double)chiR +
                                        dd * dd * chiL * (double)chiR + dd * dd * dd * dd));
-        launch_theta<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d, orient,
-                        h->stream);
+        if (sizeof(T) == 4 && h->prec == EA_C64_BF16X3)
+            launch_theta_bf16x3(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d,
+                                orient, h->stream);
+        else
+            launch_theta<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d,
+                            orient, h->stream);
     }
     LAUNCHCHK(h);
     TRY(factor_and_decide<T>(h, mw, nw, f_t, 0, forced_k));
@@ -497,6 +553,10 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
         gather<T>(h, h->W.p, N, k, N, 1, right ? 0 : -1, right ? 1 : 0, 0, h->site[i + 1].p);
     }
     LAUNCHCHK(h);
+    if (right)
+        TRY(reorth<T>(h, true, h->site[i].p, M, k, h->site[i + 1].p, N));
+    else
+        TRY(reorth<T>(h, false, h->site[i + 1].p, N, k, h->site[i].p, M));
     h->bond[i + 1] = k;
     h->center = right ? i + 1 : i;
     h->lnP += rec.lnf;

@@ -33,6 +33,11 @@ constexpr int EA_SORT_MAX = 4096;
 template <typename T>
 void launch_theta(const void *A, const void *B, const void *G, void *W, int chiL, int chiM,
                   int chiR, int d, int orient, hipStream_t s);
+// FP32 operands split into bf16 hi/lo parts on the bf16 matrix cores
+// (three products per real product, FP32 accumulation); same layout and
+// epilogue as launch_theta<float>.
+void launch_theta_bf16x3(const void *A, const void *B, const void *G, void *W, int chiL,
+                         int chiM, int chiR, int d, int orient, hipStream_t s);
 // C (M x N) = A (M x K) * B (K x N), row-major with leading dimensions.
 template <typename T>
 void launch_gemm(const void *A, const void *B, void *C, int M, int N, int K, int lda, int ldb,
@@ -120,8 +125,8 @@ void launch_scale(void *x, size_t n, double re, double im, hipStream_t s);
 // matrices, 1 = per-pair rotations, 2 = MFMA apply to W and V.
 template <typename T>
 void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
-                        double tol, int inner_max, void *partial, void *J, int *rotflag,
-                        int *rot_counter, int rot_threads, hipStream_t s);
+                        double tol, int inner_max, int inter, void *partial, void *J,
+                        int *rotflag, int *rot_counter, int rot_threads, hipStream_t s);
 size_t jacobi_round3_partial_elems(int m, int n, int w);
 size_t jacobi_round3_j_elems(int n, int w);
 
@@ -157,3 +162,6 @@ void launch_svdvjp_P(int r, const void *J, const void *K, const double *s, const
 template <typename T>
 void launch_gbar_grad(const void *Ab, const void *A, int chiL, int chiR, double *partial,
                       const double *dg, double *grad, int param, hipStream_t s);
+// Y = I - E/2, R = I + E/2 from G = I + E (k x k, complex FP64).
+template <typename T>
+void launch_reorth_factors(int k, const void *G, void *Y, void *R, hipStream_t s);

@@ -301,6 +301,28 @@ void launch_gbar_grad(const void *Ab, const void *A, int chiL, int chiR, double 
     k_gbar_final<<<1, 64, 0, s>>>(partial, nblk, dg, grad, param);
 }
 
+// From the Gram matrix G = X^H X = I + E of a nearly orthonormal factor (FP64):
+// Y = I - E/2 (the Loewdin correction X <- X Y) and R = I + E/2 (absorbed by
+// the neighbour, so that X Y R = X + O(E^2)), both stored in T.
+template <typename T>
+__global__ void k_reorth_factors(int k, const cx<double> *__restrict__ G, cx<T> *__restrict__ Y,
+                                 cx<T> *__restrict__ R) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= k * k) return;
+    const int i = idx / k, j = idx % k;
+    const double ex = G[idx].x - (i == j ? 1.0 : 0.0), ey = G[idx].y;
+    Y[idx] = mk<T>((T)((i == j ? 1.0 : 0.0) - 0.5 * ex), (T)(-0.5 * ey));
+    R[idx] = mk<T>((T)((i == j ? 1.0 : 0.0) + 0.5 * ex), (T)(0.5 * ey));
+}
+template <typename T>
+void launch_reorth_factors(int k, const void *G, void *Y, void *R, hipStream_t s) {
+    const int n = k * k;
+    k_reorth_factors<T><<<(n + 255) / 256, 256, 0, s>>>(k, (const cx<double> *)G, (cx<T> *)Y,
+                                                        (cx<T> *)R);
+}
+template void launch_reorth_factors<float>(int, const void *, void *, void *, hipStream_t);
+template void launch_reorth_factors<double>(int, const void *, void *, void *, hipStream_t);
+
 #define INST(T)                                                                                  \
     template void launch_gemm_ex<T>(int, int, int, int, int, double, double, const void *, int,  \
                                     const void *, int, double, double, void *, int, hipStream_t); \

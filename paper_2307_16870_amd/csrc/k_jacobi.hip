@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(cx<T> *__restrict__ W, int
     __shared__ cx<T> G[NC][NC + 1];
     __shared__ cx<T> J[NC][NC + 1];
     __shared__ cx<T> S[RC][NC + 1];
-    __shared__ T rc_[NP], rs_[NP], rtg_[NP], ra_[NP], rb_[NP];
+    __shared__ T rs_[NP], rgm_[NP], rtg_[NP], ra_[NP], rb_[NP];
     __shared__ cx<T> re_[NP];
     __shared__ int rp_[NP], rq_[NP], rdo_[NP];
     __shared__ int cols[NC];
@@ -112,15 +112,12 @@ __global__ __launch_bounds__(256) void k_jacobi_block(cx<T> *__restrict__ W, int
                     if (q < nc) {
                         const T al = G[p][p].x, be = G[q][q].x;
                         const cx<T> ga = G[p][q];
-                        const T g = sqrt(norm2(ga));
-                        if (g > T(0) && g > tol * sqrt(al * be)) {
-                            const T zeta = (be - al) / (T(2) * g);
-                            const T t = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + hypot(T(1), zeta));
-                            const T c = T(1) / sqrt(T(1) + t * t);
-                            rc_[tid] = c;
-                            rs_[tid] = c * t;
-                            re_[tid] = (T(1) / g) * conj(ga);
-                            rtg_[tid] = t * g;
+                        JRot<T> rt;
+                        if (jacobi_rotation(al, be, ga, tol, rt)) {
+                            rs_[tid] = rt.s;
+                            rgm_[tid] = rt.gm;
+                            re_[tid] = rt.e;
+                            rtg_[tid] = rt.tg;
                             ra_[tid] = al;
                             rb_[tid] = be;
                             dd = 1;
@@ -137,14 +134,10 @@ __global__ __launch_bounds__(256) void k_jacobi_block(cx<T> *__restrict__ W, int
                     const int pi = e / nc, row = e % nc;
                     if (rdo_[pi]) {
                         const int p = rp_[pi], q = rq_[pi];
-                        const T c = rc_[pi], s = rs_[pi];
+                        const T s = rs_[pi], gm = rgm_[pi];
                         const cx<T> ee = re_[pi];
-                        cx<T> gp = G[row][p], gq = ee * G[row][q];
-                        G[row][p] = c * gp - s * gq;
-                        G[row][q] = s * gp + c * gq;
-                        cx<T> jp = J[row][p], jq = ee * J[row][q];
-                        J[row][p] = c * jp - s * jq;
-                        J[row][q] = s * jp + c * jq;
+                        rot_pair(G[row][p], ee * G[row][q], s, gm, G[row][p], G[row][q]);
+                        rot_pair(J[row][p], ee * J[row][q], s, gm, J[row][p], J[row][q]);
                     }
                 }
                 __syncthreads();
@@ -153,11 +146,9 @@ __global__ __launch_bounds__(256) void k_jacobi_block(cx<T> *__restrict__ W, int
                     const int pi = e / nc, col = e % nc;
                     if (rdo_[pi]) {
                         const int p = rp_[pi], q = rq_[pi];
-                        const T c = rc_[pi], s = rs_[pi];
                         const cx<T> ec = conj(re_[pi]);
-                        cx<T> gp = G[p][col], gq = ec * G[q][col];
-                        G[p][col] = c * gp - s * gq;
-                        G[q][col] = s * gp + c * gq;
+                        rot_pair(G[p][col], ec * G[q][col], rs_[pi], rgm_[pi], G[p][col],
+                                 G[q][col]);
                     }
                 }
                 __syncthreads();

@@ -139,13 +139,14 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
 template <typename T, int NC, int NTH>
 __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial, int nchunks,
                                               int n, int w, int nb, int rnd, T tol,
-                                              int inner_max, cx<T> *__restrict__ Jout,
+                                              int inner_max, int inter,
+                                              cx<T> *__restrict__ Jout,
                                               int *__restrict__ rotflag,
                                               int *__restrict__ rot_counter) {
     constexpr int NP = NC / 2;
     __shared__ cx<T> G[NC][NC + 1];
     __shared__ cx<T> J[NC][NC + 1];
-    __shared__ T rc_[NP], rs_[NP], rtg_[NP], ra_[NP], rb_[NP];
+    __shared__ T rs_[NP], rgm_[NP], rtg_[NP], ra_[NP], rb_[NP];
     __shared__ cx<T> re_[NP];
     __shared__ int rp_[NP], rq_[NP], rdo_[NP];
     __shared__ int cols[NC];
@@ -172,34 +173,50 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     if (tid < 2) nrot_sh[tid] = 0;
     __syncthreads();
     const int nce = nc + (nc & 1);
-    const int npairs = nce / 2;
+    // inter = 0: every pair of the nc columns (round-robin over nce players,
+    // nce - 1 steps of nce / 2 pairs).  inter = 1: only the na x nbb pairs
+    // across the two blocks, step k pairing column i of block a with column
+    // (i + k) mod w of block b (w steps of w pairs); the pairs inside a block
+    // were rotated in the first round of the sweep.
+    const int na = max(0, min(w, n - rr_player(pair, rnd, nb) * w));
+    const int npairs = inter ? w : nce / 2;
+    const int nsteps = inter ? w : nce - 1;
     int first = 0;
-    if (nc >= 2) {
+    if (nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
             const int slot = isw & 1;
-            for (int step = 0; step < nce - 1; ++step) {
+            for (int step = 0; step < nsteps; ++step) {
                 // rotation of each disjoint pair of this step, from the current G
                 if (tid < npairs) {
-                    int p = rr_player(tid, step, nce), q = rr_player(nce - 1 - tid, step, nce);
-                    if (p > q) {
-                        const int t = p;
-                        p = q;
-                        q = t;
+                    int p, q, valid;
+                    if (inter) {
+                        // the rows p, q of all w pairs must partition the Gram
+                        // matrix: an idle slot of a short block a takes a row
+                        // past na + w (zero rows below NC) instead of one of b's
+                        const int jb = (tid + step) % w;
+                        p = tid < na ? tid : na + w + (tid - na);
+                        q = na + jb;
+                        valid = tid < na && q < nc;
+                    } else {
+                        p = rr_player(tid, step, nce);
+                        q = rr_player(nce - 1 - tid, step, nce);
+                        if (p > q) {
+                            const int t = p;
+                            p = q;
+                            q = t;
+                        }
+                        valid = q < nc;
                     }
                     int dd = 0;
-                    if (q < nc) {
+                    if (valid) {
                         const T al = G[p][p].x, be = G[q][q].x;
                         const cx<T> ga = G[p][q];
-                        const T g = sqrt(norm2(ga));
-                        if (g > T(0) && g > tol * sqrt(al * be)) {
-                            const T zeta = (be - al) / (T(2) * g);
-                            const T az = fabs(zeta);
-                            const T t = (zeta >= T(0) ? T(1) : T(-1)) / (az + (az < T(1e15) ? sqrt(T(1) + az * az) : az));
-                            const T c = T(1) / sqrt(T(1) + t * t);
-                            rc_[tid] = c;
-                            rs_[tid] = c * t;
-                            re_[tid] = (T(1) / g) * conj(ga);
-                            rtg_[tid] = t * g;
+                        JRot<T> rt;
+                        if (jacobi_rotation(al, be, ga, tol, rt)) {
+                            rs_[tid] = rt.s;
+                            rgm_[tid] = rt.gm;
+                            re_[tid] = rt.e;
+                            rtg_[tid] = rt.tg;
                             ra_[tid] = al;
                             rb_[tid] = be;
                             dd = 1;
@@ -229,20 +246,16 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                     cx<T> g00 = G[pa][pb], g01 = vb ? G[pa][qb] : zero_cx<T>();
                     cx<T> g10 = va ? G[qa][pb] : zero_cx<T>(), g11 = (va && vb) ? G[qa][qb] : zero_cx<T>();
                     if (db) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
-                        const T c = rc_[b], s = rs_[b];
+                        const T s = rs_[b], gm = rgm_[b];
                         const cx<T> ee = re_[b];
-                        const cx<T> t01 = ee * g01, t11 = ee * g11;
-                        const cx<T> n00 = c * g00 - s * t01, n01 = s * g00 + c * t01;
-                        const cx<T> n10 = c * g10 - s * t11, n11 = s * g10 + c * t11;
-                        g00 = n00; g01 = n01; g10 = n10; g11 = n11;
+                        rot_pair(g00, ee * g01, s, gm, g00, g01);
+                        rot_pair(g10, ee * g11, s, gm, g10, g11);
                     }
                     if (da) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
-                        const T c = rc_[a], s = rs_[a];
+                        const T s = rs_[a], gm = rgm_[a];
                         const cx<T> ec = conj(re_[a]);
-                        const cx<T> t10 = ec * g10, t11 = ec * g11;
-                        const cx<T> n00 = c * g00 - s * t10, n10 = s * g00 + c * t10;
-                        const cx<T> n01 = c * g01 - s * t11, n11 = s * g01 + c * t11;
-                        g00 = n00; g01 = n01; g10 = n10; g11 = n11;
+                        rot_pair(g00, ec * g10, s, gm, g00, g10);
+                        rot_pair(g01, ec * g11, s, gm, g01, g11);
                     }
                     G[pa][pb] = g00;
                     if (vb) G[pa][qb] = g01;
@@ -254,10 +267,8 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                     const int b = e / nc, row = e % nc;
                     if (rdo_[b]) {
                         const int p = rp_[b], q = rq_[b];
-                        const T c = rc_[b], s = rs_[b];
-                        const cx<T> jp = J[row][p], jq = re_[b] * J[row][q];
-                        J[row][p] = c * jp - s * jq;
-                        J[row][q] = s * jp + c * jq;
+                        rot_pair(J[row][p], re_[b] * J[row][q], rs_[b], rgm_[b], J[row][p],
+                                 J[row][q]);
                     }
                 }
                 __syncthreads();
@@ -366,8 +377,8 @@ static int rows_per_chunk(int rows, int nch) {
 
 template <typename T, int NC>
 static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
-                       double tol, int inner_max, void *partial, void *J, int *rotflag,
-                       int *rot_counter, int rot_threads, hipStream_t s) {
+                       double tol, int inner_max, int inter, void *partial, void *J,
+                       int *rotflag, int *rot_counter, int rot_threads, hipStream_t s) {
     const int npairs = nb / 2;
     const int nchG = chunks_for(m, npairs, 512);
     const int rpcG = rows_per_chunk(m, nchG);
@@ -378,7 +389,7 @@ static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, 
     } else if (part == 1) {
 #define EA_JEIG(NTH)                                                                          \
     k_jeig<T, NC, NTH><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, w, nb, rnd,   \
-                                              (T)tol, inner_max, (cx<T> *)J, rotflag,        \
+                                              (T)tol, inner_max, inter, (cx<T> *)J, rotflag, \
                                               rot_counter)
         if (rot_threads <= 64) EA_JEIG(64);
         else if (rot_threads <= 128) EA_JEIG(128);
@@ -416,17 +427,17 @@ size_t jacobi_round3_j_elems(int n, int w) {
 
 template <typename T>
 void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
-                        double tol, int inner_max, void *partial, void *J, int *rotflag,
-                        int *rot_counter, int rot_threads, hipStream_t s) {
+                        double tol, int inner_max, int inter, void *partial, void *J,
+                        int *rotflag, int *rot_counter, int rot_threads, hipStream_t s) {
     if (2 * w <= 32)
-        round_part<T, 32>(part, W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag,
-                          rot_counter, rot_threads, s);
+        round_part<T, 32>(part, W, m, V, n, w, nb, rnd, tol, inner_max, inter, partial, J,
+                          rotflag, rot_counter, rot_threads, s);
     else
-        round_part<T, 64>(part, W, m, V, n, w, nb, rnd, tol, inner_max, partial, J, rotflag,
-                          rot_counter, rot_threads, s);
+        round_part<T, 64>(part, W, m, V, n, w, nb, rnd, tol, inner_max, inter, partial, J,
+                          rotflag, rot_counter, rot_threads, s);
 }
 
 template void launch_jacobi_part<float>(int, void *, int, void *, int, int, int, int, double, int,
-                                        void *, void *, int *, int *, int, hipStream_t);
+                                        int, void *, void *, int *, int *, int, hipStream_t);
 template void launch_jacobi_part<double>(int, void *, int, void *, int, int, int, int, double,
-                                         int, void *, void *, int *, int *, int, hipStream_t);
+                                         int, int, void *, void *, int *, int *, int, hipStream_t);
