@@ -139,8 +139,8 @@ _OPS["ZZ"] = np.kron(_OPS["Z"], _OPS["Z"])
 # per precision: decision margin (relative to T) under which a kept-rank
 # decision counts as protected, and tolerances on f, ln P and observables
 _BAR = {"c128": (1e-12, 1e-10, 1e-9, 1e-8),
-        "c64": (1e-6, 2e-6, 2e-4, 2e-3),
-        "bf16x3": (1e-5, 2e-5, 2e-3, 2e-2)}
+        "c64": (1e-6, 5e-6, 4e-5, 4e-5),
+        "bf16x3": (1e-5, 5e-6, 4e-5, 4e-5)}
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
