@@ -82,13 +82,14 @@ enum ea_option {
     EA_OPT_JACOBI_TOL = 0,   /* rotate a pair if |g| > tol*sqrt(a b); default m*eps */
     EA_OPT_MAX_SWEEPS = 1,   /* default 40 */
     EA_OPT_TAU = 2,          /* numerical-zero cutoff tau*s_0; 1e-13 (FP64), 2e-6 (FP32) */
-    EA_OPT_BLOCK = 3,        /* Jacobi column-block width (0 = automatic) */
+    EA_OPT_BLOCK = 3,        /* Jacobi column-block width (0 = automatic: 32 for the
+                                three-kernel form) */
     EA_OPT_CHI_MAX = 4,      /* cap on kept rank; 0 = none */
     EA_OPT_INNER_SWEEPS = 5, /* rotation sweeps over a block pair's Gram per round (default 1) */
     EA_OPT_JACOBI_KERNEL = 6,/* 0: Gram / rotations / apply as three kernels (MFMA);
                                 1: one fused kernel per round (vector ALU) */
-    EA_OPT_ROT_THREADS = 7,  /* threads of the per-pair rotation kernel: 64, 128, 256,
-                                512 (default) or 1024 */
+    EA_OPT_ROT_THREADS = 7,  /* threads of the per-pair rotation kernel: 64, 128, 256, 512,
+                                1024, or 0 (default: 16 per column of a block pair) */
     EA_OPT_REORTH = 8,       /* FP32 precisions: 1 (default) re-orthogonalises every
                                 isometric factor in FP64 after its factorisation */
     EA_OPT_JACOBI_ORDER = 9  /* three-kernel Jacobi: 1 (default) rotates the column pairs

@@ -151,8 +151,9 @@ int mps_set_option(ea_mps *h, int option, double value) {
         h->jorder = (int)value;
         return EA_OK;
     case EA_OPT_ROT_THREADS:
-        if (value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
-            return set_err(EA_EINVAL, "rotation threads must be 64, 128, 256, 512 or 1024");
+        if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512 &&
+            value != 1024)
+            return set_err(EA_EINVAL, "rotation threads must be 0, 64, 128, 256, 512 or 1024");
         h->rot_threads = (int)value;
         return EA_OK;
     default:

@@ -91,3 +91,13 @@ __device__ __forceinline__ bool jacobi_rotation(T al_, T be_, cx<T> ga_, T tol, 
     r.e = mk<T>((T)(gx * ig), (T)(-gy * ig));
     return true;
 }
+
+// One rotation of a Jacobi step as staged in LDS for the update threads.
+template <typename T>
+struct alignas(16) RotRec {
+    T s, gm;   // sin, 1 - cos
+    cx<T> e;   // phase conj(g) / |g|
+    T tg;      // t |g|
+    T al, be;  // diagonal entries before the rotation
+    int on;    // rotation applied
+};

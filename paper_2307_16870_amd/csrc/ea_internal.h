@@ -57,7 +57,7 @@ struct ea_mps {
     ea::DevBuf jpart, jmat, jflag;
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
-    int inner_round = 1, jkernel = 0, rot_threads = 512;
+    int inner_round = 1, jkernel = 0, rot_threads = 0;  // 0: 16 per column of a block pair
     int jorder = 1;  // 1: pairs inside a column block rotated in a sweep's first round only
     ea::DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
     ea_dev_rec *rec_host = nullptr;
@@ -260,9 +260,10 @@ int svd_core(ea_mps *h, int m, int n) {
         return EA_OK;
     }
     const bool three = h->jkernel == 0;
-    int w = h->block > 0 ? h->block : (three ? 16 : (n <= 256 ? 8 : 16));
+    int w = h->block > 0 ? h->block : (three ? 32 : (n <= 256 ? 8 : 16));
     if (2 * w > 64) w = 32;
     const int ncmax = 2 * w <= 16 ? 16 : (2 * w <= 32 ? 32 : 64);
+    const int rot_threads = h->rot_threads > 0 ? h->rot_threads : (2 * w <= 32 ? 512 : 1024);
     int nb = (n + w - 1) / w;
     nb += nb & 1;
     if (three) {
@@ -292,19 +293,19 @@ int svd_core(ea_mps *h, int m, int n) {
                     ProfScope ps(h, EA_K_JGRAM, 4.0 * m * fl2, c * m * (double)n);
                     launch_jacobi_part<T>(0, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          h->rot_threads, h->stream);
+                                          rot_threads, h->stream);
                 }
                 {
                     ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * 64.0 * 64.0);
                     launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          h->rot_threads, h->stream);
+                                          rot_threads, h->stream);
                 }
                 {
                     ProfScope ps(h, EA_K_JAPPLY, 8.0 * (m + n) * fl2, 2.0 * c * (m + n) * (double)n);
                     launch_jacobi_part<T>(2, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          h->rot_threads, h->stream);
+                                          rot_threads, h->stream);
                 }
             } else {
                 ProfScope ps(h, EA_K_JFUSED, (4.0 * m + 8.0 * (m + n)) * fl2,

@@ -58,16 +58,24 @@ constexpr int JRS = 64;  // rows staged in LDS per step
 
 // Load rows [r0, r0+JRS) of the owned columns into split real/imag LDS planes,
 // zero-padding rows >= r_end and columns >= nc.
+// All loads of a thread are issued before the first LDS write, so their
+// latencies overlap instead of adding up.
 template <typename T, int NC>
 __device__ __forceinline__ void stage_rows(const cx<T> *__restrict__ X, int M, const int *cols,
                                            int nc, int r0, int r_end, T (*Sr)[NC + 1],
                                            T (*Si)[NC + 1], int tid) {
-    for (int e = tid; e < JRS * NC; e += 256) {
-        const int c = e / JRS, rr = e % JRS, row = r0 + rr;
-        cx<T> v = zero_cx<T>();
-        if (c < nc && row < r_end) v = X[(size_t)cols[c] * M + row];
-        Sr[rr][c] = v.x;
-        Si[rr][c] = v.y;
+    constexpr int PER = JRS * NC / 256;
+    cx<T> v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + 256 * i, c = e / JRS, row = r0 + e % JRS;
+        v[i] = (c < nc && row < r_end) ? X[(size_t)cols[c] * M + row] : zero_cx<T>();
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = tid + 256 * i, c = e / JRS, rr = e % JRS;
+        Sr[rr][c] = v[i].x;
+        Si[rr][c] = v[i].y;
     }
 }
 
@@ -146,9 +154,9 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     constexpr int NP = NC / 2;
     __shared__ cx<T> G[NC][NC + 1];
     __shared__ cx<T> J[NC][NC + 1];
-    __shared__ T rs_[NP], rgm_[NP], rtg_[NP], ra_[NP], rb_[NP];
-    __shared__ cx<T> re_[NP];
-    __shared__ int rp_[NP], rq_[NP], rdo_[NP];
+    static_assert((NP & (NP - 1)) == 0 && NP <= 256, "block pair width must be a power of 2");
+    __shared__ RotRec<T> rec_[NP];
+    __shared__ unsigned short tab_[NP * (NP + 1) / 2];  // packed (a, b), a <= b
     __shared__ int cols[NC];
     __shared__ int nrot_sh[2];
     const int tid = threadIdx.x, pair = blockIdx.x;
@@ -158,8 +166,20 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     for (int e = tid; e < NC * NC; e += NTH) {
         const int p = e / NC, q = e % NC;
         if (p <= q) {
+            // chunks summed in order, eight loads in flight at a time
             double sx = 0.0, sy = 0.0;
-            for (int c = 0; c < nchunks; ++c) {
+            int c = 0;
+            for (; c + 8 <= nchunks; c += 8) {
+                cx<T> v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(c + j) * NC * NC + e];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    sx += (double)v[j].x;
+                    sy += (double)v[j].y;
+                }
+            }
+            for (; c < nchunks; ++c) {
                 const cx<T> v = src[(size_t)c * NC * NC + e];
                 sx += (double)v.x;
                 sy += (double)v.y;
@@ -171,6 +191,10 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         J[p][q] = mk<T>(p == q ? T(1) : T(0), T(0));
     }
     if (tid < 2) nrot_sh[tid] = 0;
+    for (int e = tid; e < NP * NP; e += NTH) {
+        const int a = e / NP, b = e % NP;
+        if (a <= b) tab_[a * NP - a * (a - 1) / 2 + (b - a)] = (unsigned short)((a << 8) | b);
+    }
     __syncthreads();
     const int nce = nc + (nc & 1);
     // inter = 0: every pair of the nc columns (round-robin over nce players,
@@ -181,6 +205,25 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     const int na = max(0, min(w, n - rr_player(pair, rnd, nb) * w));
     const int npairs = inter ? w : nce / 2;
     const int nsteps = inter ? w : nce - 1;
+    // Columns (p, q) of pair slot `sl` at step `step`.  The p, q of all slots
+    // partition the rows of G: in the inter-block order an idle slot of a
+    // short block a takes a row past na + w (zero rows below NC).  Indices are
+    // arithmetic, so the update threads need no lookup before their loads.
+    auto slot_pq = [&](int sl, int step, int &pp, int &qq) -> bool {
+        if (inter) {
+            pp = sl < na ? sl : na + w + (sl - na);
+            qq = na + (w == NP ? ((sl + step) & (NP - 1)) : (sl + step) % w);
+            return sl < na && qq < nc;
+        }
+        pp = rr_player(sl, step, nce);
+        qq = rr_player(nce - 1 - sl, step, nce);
+        if (pp > qq) {
+            const int t = pp;
+            pp = qq;
+            qq = t;
+        }
+        return qq < nc;
+    };
     int first = 0;
     if (nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
@@ -188,88 +231,85 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
             for (int step = 0; step < nsteps; ++step) {
                 // rotation of each disjoint pair of this step, from the current G
                 if (tid < npairs) {
-                    int p, q, valid;
-                    if (inter) {
-                        // the rows p, q of all w pairs must partition the Gram
-                        // matrix: an idle slot of a short block a takes a row
-                        // past na + w (zero rows below NC) instead of one of b's
-                        const int jb = (tid + step) % w;
-                        p = tid < na ? tid : na + w + (tid - na);
-                        q = na + jb;
-                        valid = tid < na && q < nc;
-                    } else {
-                        p = rr_player(tid, step, nce);
-                        q = rr_player(nce - 1 - tid, step, nce);
-                        if (p > q) {
-                            const int t = p;
-                            p = q;
-                            q = t;
-                        }
-                        valid = q < nc;
-                    }
-                    int dd = 0;
-                    if (valid) {
+                    int p, q;
+                    RotRec<T> r;
+                    r.s = r.gm = r.tg = r.al = r.be = T(0);
+                    r.e = mk<T>(T(1), T(0));
+                    r.on = 0;
+                    if (slot_pq(tid, step, p, q)) {
                         const T al = G[p][p].x, be = G[q][q].x;
                         const cx<T> ga = G[p][q];
                         JRot<T> rt;
                         if (jacobi_rotation(al, be, ga, tol, rt)) {
-                            rs_[tid] = rt.s;
-                            rgm_[tid] = rt.gm;
-                            re_[tid] = rt.e;
-                            rtg_[tid] = rt.tg;
-                            ra_[tid] = al;
-                            rb_[tid] = be;
-                            dd = 1;
+                            r.s = rt.s;
+                            r.gm = rt.gm;
+                            r.e = rt.e;
+                            r.tg = rt.tg;
+                            r.al = al;
+                            r.be = be;
+                            r.on = 1;
                             atomicAdd(&nrot_sh[slot], 1);
                         }
                     }
-                    rp_[tid] = p;
-                    rq_[tid] = q;
-                    rdo_[tid] = dd;
+                    rec_[tid] = r;
                 }
                 __syncthreads();
-                // G <- M^H G M on 2x2 blocks (row pair a, column pair b); each block
-                // needs only its own four entries, so one pass suffices.
-                for (int e = tid; e < npairs * npairs; e += NTH) {
-                    const int a = e / npairs, b = e % npairs;
-                    const int da = rdo_[a], db = rdo_[b];
-                    if (!da && !db) continue;
-                    const int pa = rp_[a], qa = rq_[a], pb = rp_[b], qb = rq_[b];
+                // G <- M^H G M on 2x2 blocks (row pair a, column pair b), a <= b only:
+                // each block needs only its own four entries, and block (b, a) is
+                // its conjugate transpose, written alongside.  The a <= b blocks
+                // are packed (tab_) so that only as many waves as needed work.
+                for (int e = tid; e < NP * (NP + 1) / 2; e += NTH) {
+                    const int ab = tab_[e], a = ab >> 8, b = ab & 255;
+                    if (b >= npairs) continue;
+                    int pa, qa, pb, qb;
+                    slot_pq(a, step, pa, qa);
+                    slot_pq(b, step, pb, qb);
+                    const RotRec<T> ra = rec_[a], rb = rec_[b];
+                    cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g10 = G[qa][pb], g11 = G[qa][qb];
+                    if (!ra.on && !rb.on) continue;
                     if (a == b) {  // rotated pair: exact diagonal
                         G[pa][qa] = zero_cx<T>();
                         G[qa][pa] = zero_cx<T>();
-                        G[pa][pa] = mk<T>(ra_[a] - rtg_[a], T(0));
-                        G[qa][qa] = mk<T>(rb_[a] + rtg_[a], T(0));
+                        G[pa][pa] = mk<T>(ra.al - ra.tg, T(0));
+                        G[qa][qa] = mk<T>(ra.be + ra.tg, T(0));
                         continue;
                     }
                     const bool va = qa < nc, vb = qb < nc;
-                    cx<T> g00 = G[pa][pb], g01 = vb ? G[pa][qb] : zero_cx<T>();
-                    cx<T> g10 = va ? G[qa][pb] : zero_cx<T>(), g11 = (va && vb) ? G[qa][qb] : zero_cx<T>();
-                    if (db) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
-                        const T s = rs_[b], gm = rgm_[b];
-                        const cx<T> ee = re_[b];
-                        rot_pair(g00, ee * g01, s, gm, g00, g01);
-                        rot_pair(g10, ee * g11, s, gm, g10, g11);
+                    if (!vb) g01 = g11 = zero_cx<T>();
+                    if (!va) g10 = g11 = zero_cx<T>();
+                    if (rb.on) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
+                        rot_pair(g00, rb.e * g01, rb.s, rb.gm, g00, g01);
+                        rot_pair(g10, rb.e * g11, rb.s, rb.gm, g10, g11);
                     }
-                    if (da) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
-                        const T s = rs_[a], gm = rgm_[a];
-                        const cx<T> ec = conj(re_[a]);
-                        rot_pair(g00, ec * g10, s, gm, g00, g10);
-                        rot_pair(g01, ec * g11, s, gm, g01, g11);
+                    if (ra.on) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
+                        const cx<T> ec = conj(ra.e);
+                        rot_pair(g00, ec * g10, ra.s, ra.gm, g00, g10);
+                        rot_pair(g01, ec * g11, ra.s, ra.gm, g01, g11);
                     }
                     G[pa][pb] = g00;
-                    if (vb) G[pa][qb] = g01;
-                    if (va) G[qa][pb] = g10;
-                    if (va && vb) G[qa][qb] = g11;
+                    G[pb][pa] = conj(g00);
+                    if (vb) {
+                        G[pa][qb] = g01;
+                        G[qb][pa] = conj(g01);
+                    }
+                    if (va) {
+                        G[qa][pb] = g10;
+                        G[pb][qa] = conj(g10);
+                    }
+                    if (va && vb) {
+                        G[qa][qb] = g11;
+                        G[qb][qa] = conj(g11);
+                    }
                 }
                 // J <- J M on the rotated column pairs
-                for (int e = tid; e < npairs * nc; e += NTH) {
-                    const int b = e / nc, row = e % nc;
-                    if (rdo_[b]) {
-                        const int p = rp_[b], q = rq_[b];
-                        rot_pair(J[row][p], re_[b] * J[row][q], rs_[b], rgm_[b], J[row][p],
-                                 J[row][q]);
-                    }
+                for (int e = tid; e < NP * NC; e += NTH) {
+                    const int b = e / NC, row = e % NC;
+                    if (b >= npairs || row >= nc) continue;
+                    int p, q;
+                    slot_pq(b, step, p, q);
+                    const RotRec<T> rb = rec_[b];
+                    const cx<T> jp = J[row][p], jq = J[row][q];
+                    if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
                 }
                 __syncthreads();
             }
@@ -314,10 +354,17 @@ __global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx
     if (r_begin >= r_end) return;
     const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, 256);
     const cx<T> *jin = Jin + (size_t)pair * NC * NC;
-    for (int e = tid; e < NC * NC; e += 256) {
-        const cx<T> v = jin[e];
-        Jr[e / NC][e % NC] = v.x;
-        Ji[e / NC][e % NC] = v.y;
+    {
+        constexpr int PER = NC * NC / 256;
+        cx<T> v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) v[i] = jin[tid + 256 * i];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            Jr[e / NC][e % NC] = v[i].x;
+            Ji[e / NC][e % NC] = v[i].y;
+        }
     }
     for (int r0 = r_begin; r0 < r_end; r0 += JRS) {
         __syncthreads();
