@@ -144,10 +144,10 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
     }
 }
 
-template <typename T, int NC, int NTH>
+template <typename T, int NC, int NTH, int INTER>
 __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial, int nchunks,
                                               int n, int w, int nb, int rnd, T tol,
-                                              int inner_max, int inter,
+                                              int inner_max,
                                               cx<T> *__restrict__ Jout,
                                               int *__restrict__ rotflag,
                                               int *__restrict__ rot_counter) {
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     __shared__ cx<T> G[NC][NC + 1];
     __shared__ cx<T> J[NC][NC + 1];
     static_assert((NP & (NP - 1)) == 0 && NP <= 256, "block pair width must be a power of 2");
-    __shared__ RotRec<T> rec_[NP];
+    __shared__ RotRec<T> rec_[2][NP];  // this step's rotations and the next step's
     __shared__ unsigned short tab_[NP * (NP + 1) / 2];  // packed (a, b), a <= b
     __shared__ int cols[NC];
     __shared__ int nrot_sh[2];
@@ -203,6 +203,7 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     // (i + k) mod w of block b (w steps of w pairs); the pairs inside a block
     // were rotated in the first round of the sweep.
     const int na = max(0, min(w, n - rr_player(pair, rnd, nb) * w));
+    constexpr bool inter = INTER != 0;
     const int npairs = inter ? w : nce / 2;
     const int nsteps = inter ? w : nce - 1;
     // Columns (p, q) of pair slot `sl` at step `step`.  The p, q of all slots
@@ -224,36 +225,38 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         }
         return qq < nc;
     };
+    // rotation of pair slot `sl` at `step` from the current G (slot < npairs)
+    auto make_rot = [&](int sl, int step, int cnt_slot) -> RotRec<T> {
+        int p, q;
+        RotRec<T> r;
+        r.s = r.gm = r.tg = r.al = r.be = T(0);
+        r.e = mk<T>(T(1), T(0));
+        r.on = 0;
+        if (slot_pq(sl, step, p, q)) {
+            const T al = G[p][p].x, be = G[q][q].x;
+            const cx<T> ga = G[p][q];
+            JRot<T> rt;
+            if (jacobi_rotation(al, be, ga, tol, rt)) {
+                r.s = rt.s;
+                r.gm = rt.gm;
+                r.e = rt.e;
+                r.tg = rt.tg;
+                r.al = al;
+                r.be = be;
+                r.on = 1;
+                atomicAdd(&nrot_sh[cnt_slot], 1);
+            }
+        }
+        return r;
+    };
     int first = 0;
     if (nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
             const int slot = isw & 1;
+            if (tid < npairs) rec_[0][tid] = make_rot(tid, 0, slot);
+            __syncthreads();
             for (int step = 0; step < nsteps; ++step) {
-                // rotation of each disjoint pair of this step, from the current G
-                if (tid < npairs) {
-                    int p, q;
-                    RotRec<T> r;
-                    r.s = r.gm = r.tg = r.al = r.be = T(0);
-                    r.e = mk<T>(T(1), T(0));
-                    r.on = 0;
-                    if (slot_pq(tid, step, p, q)) {
-                        const T al = G[p][p].x, be = G[q][q].x;
-                        const cx<T> ga = G[p][q];
-                        JRot<T> rt;
-                        if (jacobi_rotation(al, be, ga, tol, rt)) {
-                            r.s = rt.s;
-                            r.gm = rt.gm;
-                            r.e = rt.e;
-                            r.tg = rt.tg;
-                            r.al = al;
-                            r.be = be;
-                            r.on = 1;
-                            atomicAdd(&nrot_sh[slot], 1);
-                        }
-                    }
-                    rec_[tid] = r;
-                }
-                __syncthreads();
+                const RotRec<T> *rec = rec_[step & 1];
                 // G <- M^H G M on 2x2 blocks (row pair a, column pair b), a <= b only:
                 // each block needs only its own four entries, and block (b, a) is
                 // its conjugate transpose, written alongside.  The a <= b blocks
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                     int pa, qa, pb, qb;
                     slot_pq(a, step, pa, qa);
                     slot_pq(b, step, pb, qb);
-                    const RotRec<T> ra = rec_[a], rb = rec_[b];
+                    const RotRec<T> ra = rec[a], rb = rec[b];
                     cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g10 = G[qa][pb], g11 = G[qa][qb];
                     if (!ra.on && !rb.on) continue;
                     if (a == b) {  // rotated pair: exact diagonal
@@ -301,13 +304,17 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                         G[qb][qa] = conj(g11);
                     }
                 }
-                // J <- J M on the rotated column pairs
+                __syncthreads();
+                // the next step's rotations need only the updated G: they are formed
+                // while this step's rotations are applied to J (J <- J M)
+                if (step + 1 < nsteps && tid < npairs)
+                    rec_[(step + 1) & 1][tid] = make_rot(tid, step + 1, slot);
                 for (int e = tid; e < NP * NC; e += NTH) {
                     const int b = e / NC, row = e % NC;
                     if (b >= npairs || row >= nc) continue;
                     int p, q;
                     slot_pq(b, step, p, q);
-                    const RotRec<T> rb = rec_[b];
+                    const RotRec<T> rb = rec[b];
                     const cx<T> jp = J[row][p], jq = J[row][q];
                     if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
                 }
@@ -435,9 +442,16 @@ static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, 
                                                             rpcG, (cx<T> *)partial);
     } else if (part == 1) {
 #define EA_JEIG(NTH)                                                                          \
-    k_jeig<T, NC, NTH><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, w, nb, rnd,   \
-                                              (T)tol, inner_max, inter, (cx<T> *)J, rotflag, \
-                                              rot_counter)
+    do {                                                                                      \
+        if (inter)                                                                            \
+            k_jeig<T, NC, NTH, 1><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, \
+                                                         w, nb, rnd, (T)tol, inner_max,       \
+                                                         (cx<T> *)J, rotflag, rot_counter);   \
+        else                                                                                  \
+            k_jeig<T, NC, NTH, 0><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, \
+                                                         w, nb, rnd, (T)tol, inner_max,       \
+                                                         (cx<T> *)J, rotflag, rot_counter);   \
+    } while (0)
         if (rot_threads <= 64) EA_JEIG(64);
         else if (rot_threads <= 128) EA_JEIG(128);
         else if (rot_threads <= 256) EA_JEIG(256);
