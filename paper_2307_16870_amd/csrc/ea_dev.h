@@ -67,16 +67,32 @@ __device__ __forceinline__ void rot_pair(cx<T> xp, cx<T> yq, T s, T gm, cx<T> &o
 // [[al, ga], [conj(ga), be]] of a Gram matrix (one-sided Jacobi, Hestenes):
 // tan(theta) = t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 // zeta = (be - al) / (2 |ga|), phase e = conj(ga) / |ga|.  The parameters are
-// formed in FP64 whatever the working type: formed in FP32 their rounding
-// leaves the accumulated rotation slightly non-unitary on average, which
-// over the ~n * sweeps rotations a column receives shows up as a drift of the
-// column norms (the singular values) of order 1e-5 at n = 2048.  Returns
-// false when the pair is already orthogonal to tolerance.
+// formed in FP64 whatever the working type: with FP32 working data, angles
+// formed in FP32 (one-ulp reciprocal square roots) were measured to raise the
+// end-to-end error of a 490-update circuit tenfold.  Returns false when the
+// pair is already orthogonal to tolerance.
 template <typename T>
 struct JRot {
     T s, gm, tg;  // sin, 1 - cos, t * |ga|
     cx<T> e;
 };
+// FP64 reciprocal square root and reciprocal from the hardware estimates
+// refined by two Newton steps each (y <- y (3 - x y^2) / 2, y <- y (2 - x y));
+// arguments are positive and finite here.  Far fewer dependent instructions
+// than the correctly rounded division and square root, to about one ulp.
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * fma(-x, y, 2.0);
+    y = y * fma(-x, y, 2.0);
+    return y;
+}
 template <typename T>
 __device__ __forceinline__ bool jacobi_rotation(T al_, T be_, cx<T> ga_, T tol, JRot<T> &r) {
     const double al = al_, be = be_, gx = ga_.x, gy = ga_.y;
@@ -89,6 +105,30 @@ __device__ __forceinline__ bool jacobi_rotation(T al_, T be_, cx<T> ga_, T tol, 
     r.gm = (T)(s * s / (1.0 + c));
     r.tg = (T)(t * g);
     r.e = mk<T>((T)(gx * ig), (T)(-gy * ig));
+    return true;
+}
+// FP32 working data: the same FP64 formulas with Newton-refined reciprocals
+// (their one-sided error of a fraction of an FP64 ulp is far below FP32
+// rounding, while the correctly rounded FP64 forms lengthen the critical path
+// of every Jacobi step).
+template <>
+__device__ __forceinline__ bool jacobi_rotation<float>(float al_, float be_, cx<float> ga_,
+                                                       float tol, JRot<float> &r) {
+    const double al = al_, be = be_, gx = ga_.x, gy = ga_.y;
+    const double g2 = gx * gx + gy * gy, ab = al * be;
+    if (!(g2 > 0.0)) return false;
+    const double ig = rsq_nr(g2), g = g2 * ig;
+    // g > tol sqrt(al be); a negative product (rounding of a vanishing
+    // column) never rotates, as sqrt would give NaN
+    if (!(ab >= 0.0) || !(g > (double)tol * (ab > 0.0 ? ab * rsq_nr(ab) : 0.0))) return false;
+    const double zeta = (be - al) * 0.5 * ig, az = fabs(zeta);
+    const double h = 1.0 + az * az;
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + (az < 1e150 ? h * rsq_nr(h) : az));
+    const double c = rsq_nr(1.0 + t * t), s = c * t;
+    r.s = (float)s;
+    r.gm = (float)(s * s * rcp_nr(1.0 + c));
+    r.tg = (float)(t * g);
+    r.e = mk<float>((float)(gx * ig), (float)(-gy * ig));
     return true;
 }
 
