@@ -39,6 +39,90 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# ---------------------------------------------------------------- HBM traffic
+# roofline.traffic comes from rocprofv3 counter runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) of this script, each scaled by what the same
+# counter reads for a device copy of known size (--calibrate-copy), and is
+# stored in profiles/traffic.json together with a digest of the kernel
+# sources; it is reported only while the sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2307_16870_amd", "csrc")
+COPY_BYTES = 256 << 20
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel):
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get("kernels", {}).get(kernel)
+    if e is None or d.get("source_sha256") != source_digest():
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def calibrate_copy():
+    """A plain device copy of COPY_BYTES, five times (profiled with --pmc)."""
+    import torch
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "repeats": 5}))
+
+
+def summarize_pmc(run_dir):
+    """Write run_dir/traffic.json (the content of profiles/traffic.json) from
+    counter CSVs under run_dir: fetch/ and write/ (bench run), copy_fetch/
+    and copy_write/ (calibration)."""
+    import csv
+    import glob
+
+    def per_kernel(sub, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(run_dir, sub, "**", "*counter_collection.csv"),
+                           recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").strip()
+                vals.setdefault(name, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+    cf, _ = per_kernel("copy_fetch", "FETCH_SIZE")
+    cw, _ = per_kernel("copy_write", "WRITE_SIZE")
+    copy_k = max(cf, key=cf.get)
+    f_fetch = COPY_BYTES / (cf[copy_k] * 1024.0)
+    f_write = COPY_BYTES / (cw[copy_k] * 1024.0)
+    fe, nf = per_kernel("fetch", "FETCH_SIZE")
+    wr, _ = per_kernel("write", "WRITE_SIZE")
+    out = {"source_sha256": source_digest(),
+           "calibration": {"copy_kernel": copy_k, "copy_bytes": COPY_BYTES,
+                           "fetch_KiB": cf[copy_k], "write_KiB": cw[copy_k],
+                           "fetch_factor": f_fetch, "write_factor": f_write},
+           "kernels": {}}
+    for k in fe:
+        fb = fe[k] * 1024.0 * f_fetch
+        wb = wr.get(k, 0.0) * 1024.0 * f_write
+        out["kernels"][k] = {"launches": nf[k], "fetch_bytes_per_launch": fb,
+                             "write_bytes_per_launch": wb, "hbm_bytes_per_launch": fb + wb}
+    with open(os.path.join(run_dir, "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def run_circuit(st, prog, f_min, progress=False):
     st.reset()
     st.set_schedule(f_min, prog.n_2q)
@@ -154,7 +238,15 @@ def main():
                          "independent circuits of the batched workload advanced together")
     ap.add_argument("--circuits", type=int, default=16, help="batched: number of circuits")
     ap.add_argument("--max-depth", type=int, default=12, help="batched: depth cap per circuit")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a device copy of known size (counter calibration)")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="only write DIR/traffic.json from counter CSVs under DIR")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        return summarize_pmc(args.summarize_pmc)
+    if args.calibrate_copy:
+        return calibrate_copy()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -215,7 +307,7 @@ def main():
         return {
             "kernel": kernel_of.get(name, name), "family": name, "bound": bound,
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None,
+            "traffic": traffic_for(kernel_of.get(name, name)),
             "avg_launch_ms": fd["ms"] / max(1, fd["launches"]), "launches": fd["launches"],
             "algorithmic_flops_per_launch": fd["flops"] / max(1, fd["launches"]),
             "algorithmic_bytes_per_launch": fd["bytes"] / max(1, fd["launches"]),
