@@ -221,6 +221,79 @@ def bench_batched(args, torch, C, P):
     print(json.dumps(out), flush=True)
 
 
+def bench_mpo40(args, torch, C, P):
+    """Noisy MPO workload: 40 qubits, depth 30, Haar U(4) gates each followed
+    by two-qubit depolarising noise p = 1e-3 (one fused 16x16 superoperator),
+    F_min = 0.95, chi <= 1024, d = 4 per site."""
+    prog, cfg = C.config_program(3, depth=args.depth if args.depth != 20 else 30)
+    stream = torch.cuda.current_stream()
+    st = P.EAState(prog.n_sites, "mixed", args.prec, chi_max=cfg["chi_max"], stream=stream)
+    tiny = C.config_program(3, depth=2)[0]
+    run_circuit(st, tiny, 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_circuit(st, prog, cfg["f_min"], progress=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F, _ = st.fidelity_estimate()
+    glog = st.gate_log()
+    out = {
+        "metric": "2-site gate updates/s & circuit time, noisy MPO (d = 4), 1 GPU",
+        "value": prog.n_2q / dt, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1000 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.prec == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"mpo-brickwork-haar-40q-depth{len(prog.layers)}-p1e-3-Fmin0.95-chi1024",
+                   "updates_per_step": prog.n_2q, "prec": args.prec},
+        "final_fidelity_estimate": F,
+        "capped_updates": int(sum(r["capped"] for r in glog)),
+        "max_bond": int(max(st.bond_dims())),
+    }
+    st.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_hea32(args, torch, C, P):
+    """Energy and all 640 angle derivatives of the 32-qubit, 10-layer
+    hardware-efficient ansatz (F_min = 0.999) through the adjoint; the CPU
+    oracle's adjoint on the same problem is timed beside it."""
+    import numpy as np
+    n, L = 32, 10
+    angles = C.hea_angles(n, L, seed=5)
+    terms = C.hea_hamiltonian(n)
+    dops = P.make_dops(P.hea_dops(n, L))
+    st = P.EAState(n, "pure", args.prec)
+    P.mps_energy_grad(st.h, dops, angles, terms, f_min=0.999)  # loads code objects
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E, g, lnP = P.mps_energy_grad(st.h, dops, angles, terms, f_min=0.999)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    n_upd = len(st.gate_log())
+    st.close()
+    out = {
+        "metric": "energy + 640-angle gradient evaluations/s (adjoint through truncation), 1 GPU",
+        "value": 1.0 / dt, "unit": "gradients/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": 1000 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.prec == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "hea-32q-10layers-RyRz-CZ-640angles-Fmin0.999",
+                   "two_site_updates_forward": n_upd, "prec": args.prec},
+        "energy": E, "lnP": lnP, "grad_norm": float(np.linalg.norm(g)),
+    }
+    if not args.no_cpu:
+        from oracle.adjoint import hea_energy_and_grad
+        t1 = time.perf_counter()
+        hea_energy_and_grad(angles, terms, f_min=0.999)
+        tc = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / tc, "unit": "gradients/s",
+                               "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                               "sample": f"one full energy + gradient evaluation, {tc:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,9 +306,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-layers", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--workload", default="brickwork50", choices=["brickwork50", "batched"],
+    ap.add_argument("--workload", default="brickwork50",
+                    choices=["brickwork50", "batched", "mpo40", "hea32"],
                     help="brickwork50: the 50-qubit depth-20 circuit (default); batched: "
-                         "independent circuits of the batched workload advanced together")
+                         "independent circuits of the batched workload advanced together; "
+                         "mpo40: the noisy 40-qubit MPO circuit; hea32: adjoint gradients")
     ap.add_argument("--circuits", type=int, default=16, help="batched: number of circuits")
     ap.add_argument("--max-depth", type=int, default=12, help="batched: depth cap per circuit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -261,6 +336,10 @@ def main():
     torch.cuda.init()
     if args.workload == "batched":
         return bench_batched(args, torch, C, P)
+    if args.workload == "mpo40":
+        return bench_mpo40(args, torch, C, P)
+    if args.workload == "hea32":
+        return bench_hea32(args, torch, C, P)
     stream = torch.cuda.current_stream()
     prog, cfg = C.config_program(2, depth=args.depth)
     f_min, chi_max = cfg["f_min"], cfg["chi_max"]

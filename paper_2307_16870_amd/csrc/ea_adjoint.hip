@@ -89,6 +89,22 @@ struct Ctx {
     double eta_rel = 0.0;
 };
 
+struct AdjCache {
+    Ctx x;
+    std::vector<Checkpoint> cps;
+    void release() {
+        x.tape.release();
+        x.ws.release();
+        free_buf(x.gradbuf);
+        free_buf(x.partbuf);
+        for (auto &b : x.Ab) free_buf(b);
+        x.Ab.clear();
+        for (auto &c : cps)
+            for (auto &b : c.site) free_buf(b);
+        cps.clear();
+    }
+};
+
 void cplx_mul2(const double *a, const double *b, double *c) {  // 2x2 complex, row-major
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
@@ -508,8 +524,8 @@ int reverse_tape(Ctx &x, const std::vector<Rec> &tape) {
         case R_EX: TRY(rev_ex<T>(x, *it)); break;
         default: TRY(rev_move<T>(x, *it)); break;
         }
-        // the workspace is reused by the next record: finish this one first
-        HIPCHK(x.h, hipStreamSynchronize(x.h->stream));
+        // the workspace is reused by the next record; all kernels are on one
+        // stream, so the next record's kernels start after this record's
     }
     return EA_OK;
 }
@@ -550,24 +566,29 @@ int energy_grad_impl(ea_mps *h, int n_ops, const ea_dop *ops, const double *para
                      int n_terms, const int *sites, const int *widths, const double *term_ops,
                      const double *coefs, double f_min, double eta_rel, double *E_out,
                      double *grad_out, double *lnP_out) {
-    Ctx x;
+    // device buffers (tape, workspace, adjoints, checkpoints) persist in the
+    // handle between calls and are released by mps_free
+    if (!h->adj) {
+        h->adj = new AdjCache();
+        h->adj_free = [](void *p) {
+            AdjCache *c = static_cast<AdjCache *>(p);
+            c->release();
+            delete c;
+        };
+    }
+    AdjCache &cache = *static_cast<AdjCache *>(h->adj);
+    Ctx &x = cache.x;
     x.h = h;
     x.eta_rel = eta_rel;
-    std::vector<Checkpoint> cps;
+    x.tape.reset();
+    x.ws.reset();
+    std::vector<Checkpoint> &cps = cache.cps;
     struct Cleanup {
-        Ctx &x;
-        std::vector<Checkpoint> &cps;
+        ea_mps *h;
         ~Cleanup() {
-            if (x.h->stream) (void)hipStreamSynchronize(x.h->stream);
-            x.tape.release();
-            x.ws.release();
-            free_buf(x.gradbuf);
-            free_buf(x.partbuf);
-            for (auto &b : x.Ab) free_buf(b);
-            for (auto &c : cps)
-                for (auto &b : c.site) free_buf(b);
+            if (h->stream) (void)hipStreamSynchronize(h->stream);
         }
-    } cleanup{x, cps};
+    } cleanup{h};
 
     TRY(mps_reset_product(h, nullptr));
     long n2 = 0;

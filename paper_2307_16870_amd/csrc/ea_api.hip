@@ -97,6 +97,8 @@ void mps_free(ea_mps *h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     prof_harvest(h);
+    if (h->adj_free) h->adj_free(h->adj);
+    h->adj = nullptr;
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     for (auto &b : h->site) free_buf(b);
     DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,

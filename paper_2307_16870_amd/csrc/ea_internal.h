@@ -58,6 +58,8 @@ struct ea_mps {
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
     int inner_round = 1, jkernel = 0, rot_threads = 0;  // 0: 16 per column of a block pair
+    void *adj = nullptr;                 // adjoint buffers kept between calls
+    void (*adj_free)(void *) = nullptr;
     int jorder = 1;  // 1: pairs inside a column block rotated in a sweep's first round only
     ea::DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
     ea_dev_rec *rec_host = nullptr;
