@@ -92,11 +92,16 @@ enum ea_option {
                                 1024, or 0 (default: 16 per column of a block pair) */
     EA_OPT_REORTH = 8,       /* FP32 precisions: 1 (default) re-orthogonalises every
                                 isometric factor in FP64 after its factorisation */
-    EA_OPT_JACOBI_ORDER = 9  /* three-kernel Jacobi: 1 (default) rotates the column pairs
+    EA_OPT_JACOBI_ORDER = 9, /* three-kernel Jacobi: 1 (default) rotates the column pairs
                                 inside a block in the first round of a sweep only, later
                                 rounds rotate only pairs across the two blocks (every pair
                                 once per sweep); 0 rotates all pairs of the block pair in
                                 every round */
+    EA_OPT_SMALL_LAYERS = 10 /* 1 (default): a layer whose every bond is at most 64 / d
+                                runs as one device-resident launch (sizes read on the
+                                device, no host synchronisation between its gates;
+                                mps_apply_layer and mps_apply_layer_batched, where all
+                                such states share one launch); 0: host-orchestrated */
 };
 
 /* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */

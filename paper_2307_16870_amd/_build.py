@@ -22,7 +22,7 @@ LIBDIR = os.path.join(PKG, "_lib")
 OBJDIR = os.path.join(PKG, "_build")
 LIBNAME = "libeamps.so"
 
-SOURCES = ["k_linalg.hip", "k_theta3.hip", "k_jacobi.hip", "k_jacobi2.hip", "k_observe.hip", "k_adjoint.hip",
+SOURCES = ["k_linalg.hip", "k_theta3.hip", "k_jacobi.hip", "k_jacobi2.hip", "k_observe.hip", "k_small.hip", "k_adjoint.hip",
            "ea_api.hip", "ea_adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -103,7 +103,8 @@ void mps_free(ea_mps *h) {
     for (auto &b : h->site) free_buf(b);
     DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
-                      &h->stage_dev};
+                      &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_gsite,
+                      &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs};
     for (DevBuf *b : bufs) free_buf(*b);
     if (h->stage_host) (void)hipHostFree(h->stage_host);
     if (h->rec_host) (void)hipHostFree(h->rec_host);
@@ -147,6 +148,10 @@ int mps_set_option(ea_mps *h, int option, double value) {
     case EA_OPT_REORTH:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "reorth must be 0 or 1");
         h->reorth = value != 0;
+        return EA_OK;
+    case EA_OPT_SMALL_LAYERS:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "small layers must be 0 or 1");
+        h->small_layers = value != 0;
         return EA_OK;
     case EA_OPT_JACOBI_ORDER:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi order must be 0 or 1");
@@ -193,8 +198,12 @@ int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget, 
                   : apply_2q_impl<float>(h, site, op, fidelity_budget, +1, f_out, 0);
 }
 
-int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
-                    const double *budgets, double *f_out) {
+}  // extern "C"
+
+namespace {
+// Argument checks of one layer; lo/hi receive the lowest and highest left site.
+int validate_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
+                   const double *budgets, int *lo_out, int *hi_out) {
     TRY(check(h));
     if (n_gates < 0) return set_err(EA_EINVAL, "n_gates < 0");
     if (n_gates == 0) return EA_OK;
@@ -213,6 +222,194 @@ int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
             return set_err(EA_EINVAL, "bad budget for gate %d", j);
     }
     if (!finite_cplx(ops, nop * n_gates)) return set_err(EA_EINVAL, "non-finite operator");
+    if (lo_out) *lo_out = lo;
+    if (hi_out) *hi_out = hi;
+    return EA_OK;
+}
+
+// A layer qualifies for the device-resident path when every bond is at most
+// SM_N / d: then every factorisation of the layer has at most SM_N columns.
+bool small_eligible(const ea_mps *h, int n_gates) {
+    if (!h->small_layers || n_gates < 1 || n_gates > SM_GATES) return false;
+    const int lim = SM_N / h->d;
+    for (int b : h->bond)
+        if (b > lim) return false;
+    return true;
+}
+
+// Upload one state's layer and fill its descriptor (host copy).
+template <typename T>
+int small_prepare(ea_mps *h, int n_gates, const int *sites, const double *ops,
+                  const double *budgets, bool want_f, SmallDesc<T> &D) {
+    const int d = h->d;
+    const size_t cap = (size_t)SM_N * d * SM_N;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->n; ++i) {  // grow the site buffers, keeping their tensors
+        if (h->site[i].bytes >= h->csz * cap) continue;
+        DevBuf nb;
+        TRY(ensure(h, nb, h->csz * cap));
+        const size_t used = h->csz * (size_t)h->bond[i] * d * h->bond[i + 1];
+        if (used > 0 && h->site[i].p)
+            HIPCHK(h, hipMemcpy(nb.p, h->site[i].p, used, hipMemcpyDeviceToDevice));
+        free_buf(h->site[i]);
+        h->site[i] = nb;
+    }
+    TRY(ensure(h, h->sm_scratch, small_scratch_bytes(h->csz)));
+    TRY(ensure(h, h->sm_sites, sizeof(void *) * h->n));
+    TRY(ensure(h, h->sm_bond, sizeof(int) * (h->n + 1)));
+    TRY(ensure(h, h->sm_gsite, sizeof(int) * SM_GATES));
+    TRY(ensure(h, h->sm_gmat, h->csz * (size_t)SM_GATES * d * d * d * d));
+    TRY(ensure(h, h->sm_budget, sizeof(double) * SM_GATES));
+    TRY(ensure(h, h->sm_log, sizeof(ea_gate_record) * SM_GATES));
+    TRY(ensure(h, h->sm_fout, sizeof(double) * SM_GATES));
+    std::vector<void *> ptrs(h->n);
+    for (int i = 0; i < h->n; ++i) ptrs[i] = h->site[i].p;
+    const size_t nop = (size_t)d * d * d * d;
+    std::vector<T> g(2 * nop * n_gates);
+    for (size_t e = 0; e < g.size(); ++e) g[e] = (T)ops[e];
+    HIPCHK(h, hipMemcpy(h->sm_sites.p, ptrs.data(), sizeof(void *) * h->n, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->sm_bond.p, h->bond.data(), sizeof(int) * (h->n + 1),
+                        hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->sm_gsite.p, sites, sizeof(int) * n_gates, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->sm_gmat.p, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice));
+    if (budgets)
+        HIPCHK(h, hipMemcpy(h->sm_budget.p, budgets, sizeof(double) * n_gates,
+                            hipMemcpyHostToDevice));
+    D = SmallDesc<T>{};
+    D.site = (cx<T> *const *)h->sm_sites.p;
+    D.bond = (int *)h->sm_bond.p;
+    D.scratch = (cx<T> *)h->sm_scratch.p;
+    D.gsite = (const int *)h->sm_gsite.p;
+    D.gmat = (const cx<T> *)h->sm_gmat.p;
+    D.budget = budgets ? (const double *)h->sm_budget.p : nullptr;
+    D.log = (ea_gate_record *)h->sm_log.p;
+    D.fout = want_f ? (double *)h->sm_fout.p : nullptr;
+    D.tau = h->tau;
+    D.tol_user = h->tol;
+    D.f_min = h->f_min;
+    D.lnP = h->lnP;
+    D.lnS = h->lnS;
+    D.n_total = h->n_total;
+    D.g = h->g;
+    D.n = h->n;
+    D.d = d;
+    D.kind = h->kind;
+    D.n_gates = n_gates;
+    D.center = h->center;
+    D.chi_max = h->chi_max;
+    D.max_sweeps = h->max_sweeps;
+    D.inner = h->inner_max;
+    D.has_sched = h->has_sched ? 1 : 0;
+    D.strategy = h->strategy;
+    D.reorth = h->reorth ? 1 : 0;
+    return EA_OK;
+}
+
+// Read back one state's layer; returns its status.
+template <typename T>
+int small_finish(ea_mps *h, const SmallDesc<T> &D, double *f_out) {
+    HIPCHK(h, hipMemcpy(h->bond.data(), h->sm_bond.p, sizeof(int) * (h->n + 1),
+                        hipMemcpyDeviceToHost));
+    std::vector<ea_gate_record> recs(D.n_done);
+    if (D.n_done > 0)
+        HIPCHK(h, hipMemcpy(recs.data(), h->sm_log.p, sizeof(ea_gate_record) * D.n_done,
+                            hipMemcpyDeviceToHost));
+    if (f_out && D.n_gates > 0)
+        HIPCHK(h, hipMemcpy(f_out, h->sm_fout.p, sizeof(double) * D.n_gates,
+                            hipMemcpyDeviceToHost));
+    for (auto &r : recs) h->log.push_back(r);
+    h->center = D.center;
+    h->lnP = D.lnP;
+    h->lnS = D.lnS;
+    h->g = D.g;
+    if (D.status < 0)
+        return set_err(D.status, "the operator annihilates the state (all singular values 0)");
+    int rc = EA_OK;
+    if (D.n_noconv > 0) rc = std::max(rc, (int)EA_WARN_NOCONV);
+    if (D.n_capped > 0) rc = std::max(rc, (int)EA_WARN_CAPPED);
+    return rc;
+}
+
+// All eligible states of one precision in one launch (one workgroup each).
+template <typename T>
+void small_batch(const std::vector<int> &idx, ea_mps *const *hs, const int *n_gates,
+                 const int *const *sites, const double *const *ops,
+                 const double *const *budgets, double *const *f_out, std::vector<int> &rc,
+                 std::vector<std::string> &err) {
+    if (idx.empty()) return;
+    std::vector<SmallDesc<T>> descs(idx.size());
+    std::vector<int> ok(idx.size(), 0);
+    for (size_t u = 0; u < idx.size(); ++u) {
+        const int b = idx[u];
+        const int r = small_prepare<T>(hs[b], n_gates[b], sites[b], ops[b],
+                                       budgets ? budgets[b] : nullptr, f_out && f_out[b],
+                                       descs[u]);
+        if (r < 0) {
+            rc[b] = r;
+            err[b] = g_err;
+        } else {
+            ok[u] = 1;
+        }
+    }
+    std::vector<SmallDesc<T>> run;
+    std::vector<int> run_u;
+    for (size_t u = 0; u < idx.size(); ++u)
+        if (ok[u]) {
+            run.push_back(descs[u]);
+            run_u.push_back((int)u);
+        }
+    if (run.empty()) return;
+    ea_mps *h0 = hs[idx[run_u[0]]];
+    auto fail_all = [&](int r) {
+        for (int u : run_u) {
+            rc[idx[u]] = r;
+            err[idx[u]] = g_err;
+        }
+    };
+    int r = ensure(h0, h0->sm_descs, sizeof(SmallDesc<T>) * run.size());
+    if (r < 0) return fail_all(r);
+    if (hipMemcpy(h0->sm_descs.p, run.data(), sizeof(SmallDesc<T>) * run.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return fail_all(set_err(EA_EHIP, "descriptor upload failed"));
+    launch_layer_small<T>((SmallDesc<T> *)h0->sm_descs.p, (int)run.size(), h0->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h0->stream);
+    if (e != hipSuccess) return fail_all(set_err(EA_EHIP, "small layer: %s", hipGetErrorString(e)));
+    if (hipMemcpy(run.data(), h0->sm_descs.p, sizeof(SmallDesc<T>) * run.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return fail_all(set_err(EA_EHIP, "descriptor read-back failed"));
+    for (size_t v = 0; v < run.size(); ++v) {
+        const int b = idx[run_u[v]];
+        rc[b] = small_finish<T>(hs[b], run[v], f_out ? f_out[b] : nullptr);
+        if (rc[b] != EA_OK) err[b] = g_err;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
+                    const double *budgets, double *f_out) {
+    int lo = 0, hi = 0;
+    TRY(validate_layer(h, n_gates, sites, ops, budgets, &lo, &hi));
+    if (n_gates == 0) return EA_OK;
+    if (small_eligible(h, n_gates)) {  // the whole layer in one device-resident launch
+        std::vector<int> idx{0}, rc1(1, EA_OK);
+        std::vector<std::string> err1(1);
+        ea_mps *hs1[1] = {h};
+        const int ng1[1] = {n_gates};
+        const int *s1[1] = {sites};
+        const double *o1[1] = {ops};
+        const double *b1[1] = {budgets};
+        double *f1[1] = {f_out};
+        if (h->f64)
+            small_batch<double>(idx, hs1, ng1, s1, o1, b1, f1, rc1, err1);
+        else
+            small_batch<float>(idx, hs1, ng1, s1, o1, b1, f1, rc1, err1);
+        if (rc1[0] != EA_OK) g_err = err1[0];
+        return rc1[0];
+    }
+    const size_t nop = (size_t)h->d * h->d * h->d * h->d;
     std::vector<int> order(n_gates);
     for (int j = 0; j < n_gates; ++j) order[j] = j;
     const bool asc = std::abs(h->center - lo) <= std::abs(h->center - hi);
@@ -247,15 +444,34 @@ int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
     }
     std::vector<int> rc(n_states, EA_OK);
     std::vector<std::string> err(n_states);
+    // states whose bonds are all small: one device-resident launch per
+    // precision; the others: one host thread and stream each
+    std::vector<int> small32, small64, big;
+    for (int b = 0; b < n_states; ++b) {
+        if (n_gates[b] > 0 && small_eligible(hs[b], n_gates[b])) {
+            int r = validate_layer(hs[b], n_gates[b], sites[b], ops[b],
+                                   budgets ? budgets[b] : nullptr, nullptr, nullptr);
+            if (r < 0) {
+                rc[b] = r;
+                err[b] = g_err;
+                continue;
+            }
+            (hs[b]->f64 ? small64 : small32).push_back(b);
+        } else {
+            big.push_back(b);
+        }
+    }
     auto work = [&](int b) {
         rc[b] = mps_apply_layer(hs[b], n_gates[b], sites[b], ops[b], budgets ? budgets[b] : nullptr,
                                 f_out ? f_out[b] : nullptr);
         if (rc[b] != EA_OK) err[b] = g_err;
     };
     std::vector<std::thread> pool;
-    pool.reserve(n_states);
-    for (int b = 1; b < n_states; ++b) pool.emplace_back(work, b);
-    work(0);
+    pool.reserve(big.size());
+    for (size_t u = 1; u < big.size(); ++u) pool.emplace_back(work, big[u]);
+    small_batch<float>(small32, hs, n_gates, sites, ops, budgets, f_out, rc, err);
+    small_batch<double>(small64, hs, n_gates, sites, ops, budgets, f_out, rc, err);
+    if (!big.empty()) work(big[0]);
     for (auto &t : pool) t.join();
     int worst = EA_OK, worst_b = -1;
     for (int b = 0; b < n_states; ++b) {

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include "ea_dev.h"
+#include "ea_mps.h"
+
 // Result of one truncation decision, written by the device, read by the host.
 struct ea_dev_rec {
     int k;        // kept rank
@@ -165,3 +168,33 @@ void launch_gbar_grad(const void *Ab, const void *A, int chiL, int chiR, double 
 // Y = I - E/2, R = I + E/2 from G = I + E (k x k, complex FP64).
 template <typename T>
 void launch_reorth_factors(int k, const void *G, void *Y, void *R, hipStream_t s);
+
+// ---- device-resident small-bond layers (k_small.hip) ----
+constexpr int SM_N = 64;       // columns of a factorisation
+constexpr int SM_M = 256;      // rows of a factorisation
+constexpr int SM_GATES = 256;  // gates of one state's layer
+// bytes of per-state scratch: W, X, P (SM_M x SM_N), V, Y, R (SM_N x SM_N)
+// in the working precision, then an SM_N x SM_N complex FP64 Gram
+inline size_t small_scratch_bytes(size_t csz) {
+    return csz * (3 * (size_t)SM_M * SM_N + 3 * (size_t)SM_N * SM_N) +
+           16 * (size_t)SM_N * SM_N;
+}
+// One state of a small-bond layer; read and updated by its workgroup.
+template <typename T>
+struct SmallDesc {
+    cx<T> *const *site;    // device array of n site pointers
+    int *bond;             // device, n + 1 bond dimensions
+    cx<T> *scratch;        // small_scratch_bytes
+    const int *gsite;      // left sites of this layer's gates (caller's order)
+    const cx<T> *gmat;     // d^4 complex per gate
+    const double *budget;  // per-gate target (< 0: schedule), or null
+    ea_gate_record *log;   // one record per gate, in visiting order
+    double *fout;          // per-gate f (caller's order), or null
+    double tau, tol_user, f_min, lnP, lnS;
+    long long n_total, g;
+    int n, d, kind, n_gates, center, asc;
+    int chi_max, max_sweeps, inner, has_sched, strategy, reorth;
+    int status, n_capped, n_noconv, n_done;
+};
+template <typename T>
+void launch_layer_small(SmallDesc<T> *descs, int n_states, hipStream_t s);
