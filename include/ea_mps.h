@@ -97,8 +97,9 @@ enum ea_option {
                                 rounds rotate only pairs across the two blocks (every pair
                                 once per sweep); 0 rotates all pairs of the block pair in
                                 every round */
-    EA_OPT_SMALL_LAYERS = 10 /* 1 (default): a layer whose every bond is at most 64 / d
-                                runs as one device-resident launch (sizes read on the
+    EA_OPT_SMALL_LAYERS = 10 /* c = 64 (default) or 128: a layer whose every bond is at
+                                most c / d runs as one device-resident launch (one
+                                workgroup per state walks the layer, sizes read on the
                                 device, no host synchronisation between its gates;
                                 mps_apply_layer and mps_apply_layer_batched, where all
                                 such states share one launch); 0: host-orchestrated */

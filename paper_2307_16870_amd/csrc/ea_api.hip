@@ -150,8 +150,9 @@ int mps_set_option(ea_mps *h, int option, double value) {
         h->reorth = value != 0;
         return EA_OK;
     case EA_OPT_SMALL_LAYERS:
-        if (value != 0 && value != 1) return set_err(EA_EINVAL, "small layers must be 0 or 1");
-        h->small_layers = value != 0;
+        if (value != 0 && value != 64 && value != SM_N)
+            return set_err(EA_EINVAL, "small layers must be 0, 64 or %d", SM_N);
+        h->small_cols = (int)value;
         return EA_OK;
     case EA_OPT_JACOBI_ORDER:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi order must be 0 or 1");
@@ -228,10 +229,11 @@ int validate_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
 }
 
 // A layer qualifies for the device-resident path when every bond is at most
-// SM_N / d: then every factorisation of the layer has at most SM_N columns.
+// small_cols / d: then every factorisation of the layer has at most small_cols
+// (<= SM_N) columns.
 bool small_eligible(const ea_mps *h, int n_gates) {
-    if (!h->small_layers || n_gates < 1 || n_gates > SM_GATES) return false;
-    const int lim = SM_N / h->d;
+    if (h->small_cols <= 0 || n_gates < 1 || n_gates > SM_GATES) return false;
+    const int lim = h->small_cols / h->d;
     for (int b : h->bond)
         if (b > lim) return false;
     return true;
@@ -242,7 +244,7 @@ template <typename T>
 int small_prepare(ea_mps *h, int n_gates, const int *sites, const double *ops,
                   const double *budgets, bool want_f, SmallDesc<T> &D) {
     const int d = h->d;
-    const size_t cap = (size_t)SM_N * d * SM_N;
+    const size_t cap = SM_ELEMS;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int i = 0; i < h->n; ++i) {  // grow the site buffers, keeping their tensors
         if (h->site[i].bytes >= h->csz * cap) continue;

@@ -65,7 +65,7 @@ struct ea_mps {
     // device-resident small-bond layers
     ea::DevBuf sm_scratch, sm_sites, sm_bond, sm_gsite, sm_gmat, sm_budget, sm_log, sm_fout,
         sm_descs;
-    bool small_layers = true;
+    int small_cols = 64;  // device-resident layers: largest factorisation width (0: off)
     ea_dev_rec *rec_host = nullptr;
     int *int_host = nullptr;
     double *dbl_host = nullptr;

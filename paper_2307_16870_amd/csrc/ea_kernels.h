@@ -170,15 +170,14 @@ template <typename T>
 void launch_reorth_factors(int k, const void *G, void *Y, void *R, hipStream_t s);
 
 // ---- device-resident small-bond layers (k_small.hip) ----
-constexpr int SM_N = 64;       // columns of a factorisation
-constexpr int SM_M = 256;      // rows of a factorisation
+constexpr int SM_N = 128;      // columns of a factorisation (bonds <= SM_N / d)
 constexpr int SM_GATES = 256;  // gates of one state's layer
-// bytes of per-state scratch: W, X, P (SM_M x SM_N), V, Y, R (SM_N x SM_N)
-// in the working precision, then an SM_N x SM_N complex FP64 Gram
-inline size_t small_scratch_bytes(size_t csz) {
-    return csz * (3 * (size_t)SM_M * SM_N + 3 * (size_t)SM_N * SM_N) +
-           16 * (size_t)SM_N * SM_N;
-}
+// Every matrix of a small-bond layer (factor, right factor, products, site
+// tensors) holds at most SM_N^2 complex entries.  Scratch per state: W, V,
+// X, P, Y, R of SM_N^2 entries in the working precision, then an SM_N^2
+// complex FP64 Gram.
+constexpr size_t SM_ELEMS = (size_t)SM_N * SM_N;
+inline size_t small_scratch_bytes(size_t csz) { return csz * 6 * SM_ELEMS + 16 * SM_ELEMS; }
 // One state of a small-bond layer; read and updated by its workgroup.
 template <typename T>
 struct SmallDesc {

@@ -1,5 +1,6 @@
 // Body of the one-sided block Jacobi workgroup (see k_jacobi.hip); shared by
 // the per-round kernel and by the device-resident small-bond layer kernel.
+// `pair` selects the block pair of round `rnd` when single = 0.
 #pragma once
 #include "ea_dev.h"
 
@@ -9,7 +10,7 @@ __device__ __forceinline__ void jacobi_block_body(cx<T> *__restrict__ W, int m,
                                                       int nb, int rnd, T tol, int inner_max,
                                                       int single, int max_outer,
                                                       int *__restrict__ rot_counter,
-                                                      int *__restrict__ sweeps_out) {
+                                                      int *__restrict__ sweeps_out, int pair) {
     constexpr int RC = (NC >= 64 && sizeof(T) == 8) ? 16 : 32;
     constexpr int NP = NC / 2;
     constexpr int EPT = (NC * NC + 255) / 256;  // Gram entries per thread
@@ -28,7 +29,7 @@ __device__ __forceinline__ void jacobi_block_body(cx<T> *__restrict__ W, int m,
         nc = n;
         for (int c = tid; c < n; c += nth) cols[c] = c;
     } else {
-        const int a = rr_player(blockIdx.x, rnd, nb), b = rr_player(nb - 1 - blockIdx.x, rnd, nb);
+        const int a = rr_player(pair, rnd, nb), b = rr_player(nb - 1 - pair, rnd, nb);
         const int a0 = a * w, a1 = min(a0 + w, n), b0 = b * w, b1 = min(b0 + w, n);
         const int na = max(0, a1 - a0), nbb = max(0, b1 - b0);
         nc = na + nbb;

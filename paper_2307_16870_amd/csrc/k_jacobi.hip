@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_jacobi_block(cx<T> *__restrict__ W, int
                                                       int *__restrict__ rot_counter,
                                                       int *__restrict__ sweeps_out) {
     jacobi_block_body<T, NC>(W, m, V, n, w, nb, rnd, tol, inner_max, single, max_outer,
-                             rot_counter, sweeps_out);
+                             rot_counter, sweeps_out, blockIdx.x);
 }
 
 template <typename T>

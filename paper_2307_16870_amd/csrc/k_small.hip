@@ -6,9 +6,11 @@
 // with exact factorisations (Sec. III) and applying each update: contraction
 // with the gate, one-sided Jacobi SVD, kept-rank rule in FP64, write-back,
 // running fidelity estimate (Eq. 12) and the target schedule (Eq. 14).
-// Valid while every factorisation has at most SM_N columns and SM_M rows,
-// which holds for a whole layer when every bond is at most SM_N / d when the
-// layer starts (the host checks this).
+// Valid while every matrix of the layer has at most SM_N^2 entries and every
+// factorisation at most SM_N columns, which holds for a whole layer when every
+// bond is at most SM_N / d when the layer starts (the host checks this).
+// Factorisations with more than 64 columns run the block round-robin Jacobi
+// (pairs of 32-column blocks) inside the workgroup.
 #include "ea_dev.h"
 #include "ea_kernels.h"
 #include "jacobi_body.h"
@@ -36,12 +38,12 @@ __device__ Work<T> work_of(const SmallDesc<T> &D) {
     Work<T> w;
     cx<T> *b = D.scratch;
     w.W = b;
-    w.V = b + (size_t)SM_M * SM_N;
-    w.X = w.V + (size_t)SM_N * SM_N;
-    w.P = w.X + (size_t)SM_M * SM_N;
-    w.Y = w.P + (size_t)SM_M * SM_N;
-    w.R = w.Y + (size_t)SM_N * SM_N;
-    w.G64 = reinterpret_cast<double *>(w.R + (size_t)SM_N * SM_N);
+    w.V = b + SM_ELEMS;
+    w.X = w.V + SM_ELEMS;
+    w.P = w.X + SM_ELEMS;
+    w.Y = w.P + SM_ELEMS;
+    w.R = w.Y + SM_ELEMS;
+    w.G64 = reinterpret_cast<double *>(w.R + SM_ELEMS);
     return w;
 }
 
@@ -68,7 +70,7 @@ __device__ double schedule_target_dev(int has_sched, int strategy, double f_min,
 template <typename T>
 __device__ void factor(const SmallDesc<T> &D, const Work<T> &w, int m, int n, int mode,
                        double f_t, Dec &dec, double *s_raw, double *s_sorted, int *perm,
-                       double *Dsuf, double *part, int *sw) {
+                       double *Dsuf, double *part, int *sw, int *cnt) {
     const int tid = threadIdx.x;
     for (int e = tid; e < n * n; e += NTH) {
         const int c = e / n, r = e % n;
@@ -77,14 +79,43 @@ __device__ void factor(const SmallDesc<T> &D, const Work<T> &w, int m, int n, in
     __syncthreads();
     const double tol = D.tol_user > 0 ? D.tol_user
                                       : (double)m * (sizeof(T) == 8 ? 0x1p-53 : 0x1p-24);
-    jacobi_block_body<T, SM_N>(w.W, m, w.V, n, n, 1, 0, (T)tol, D.inner, 1, D.max_sweeps,
-                               nullptr, sw);
+    if (n <= 64) {  // all columns in one Gram matrix
+        jacobi_block_body<T, 64>(w.W, m, w.V, n, n, 1, 0, (T)tol, D.inner, 1, D.max_sweeps,
+                                 nullptr, sw, 0);
+    } else {  // blocks of 32 columns, round-robin over block pairs
+        const int bw = 32;
+        int nb = (n + bw - 1) / bw;
+        nb += nb & 1;
+        int sweeps = 0, conv = 0;
+        for (int s = 0; s < D.max_sweeps; ++s) {
+            if (tid == 0) cnt[0] = 0;
+            __syncthreads();
+            for (int rnd = 0; rnd < nb - 1; ++rnd)
+                for (int pr = 0; pr < nb / 2; ++pr) {
+                    jacobi_block_body<T, 64>(w.W, m, w.V, n, bw, nb, rnd, (T)tol, D.inner, 0, 1,
+                                             cnt, nullptr, pr);
+                    __syncthreads();
+                }
+            ++sweeps;
+            const int c = cnt[0];
+            __syncthreads();
+            if (c == 0) {
+                conv = 1;
+                break;
+            }
+        }
+        if (tid == 0) {
+            sw[0] = sweeps;
+            sw[1] = conv;
+        }
+    }
     __syncthreads();
-    {  // four threads per column
-        const int j = tid >> 2, q = tid & 3;
+    {  // tpc threads per column
+        const int tpc = n <= 64 ? 4 : 2;
+        const int j = tid / tpc, q = tid % tpc;
         double a = 0.0;
         if (j < n)
-            for (int i = q; i < m; i += 4) {
+            for (int i = q; i < m; i += tpc) {
                 const cx<T> v = w.W[(size_t)j * m + i];
                 a += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
             }
@@ -92,7 +123,9 @@ __device__ void factor(const SmallDesc<T> &D, const Work<T> &w, int m, int n, in
     }
     __syncthreads();
     if (tid < n) {
-        const double a = part[4 * tid] + part[4 * tid + 1] + part[4 * tid + 2] + part[4 * tid + 3];
+        const int tpc = n <= 64 ? 4 : 2;
+        double a = 0.0;
+        for (int u = 0; u < tpc; ++u) a += part[tpc * tid + u];
         s_raw[tid] = sqrt(a);
     }
     __syncthreads();
@@ -241,7 +274,7 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
     const Work<T> w = work_of(D);
     __shared__ Dec dec;
     __shared__ double s_raw[SM_N], s_sorted[SM_N], Dsuf[SM_N + 1], part[NTH];
-    __shared__ int perm[SM_N], order[SM_GATES], sw[2];
+    __shared__ int perm[SM_N], order[SM_GATES], sw[2], cnt[1];
     __shared__ int center_sh, stop_sh;
     const int tid = threadIdx.x, d = D.d, ng = D.n_gates;
     int *bond = D.bond;
@@ -286,7 +319,7 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
                     else w.W[e] = conj(v);
                 }
                 __syncthreads();
-                factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw);
+                factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
                 if (!(dec.s0 > 0.0)) {
                     if (tid == 0) {
                         D.status = EA_EINVAL;
@@ -320,7 +353,7 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
                     else w.W[e] = conj(v);
                 }
                 __syncthreads();
-                factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw);
+                factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
                 if (!(dec.s0 > 0.0)) {
                     if (tid == 0) {
                         D.status = EA_EINVAL;
@@ -380,7 +413,7 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
                 w.W[(size_t)row * N + col] = conj(th);
         }
         __syncthreads();
-        factor<T>(D, w, mw, nw, 0, f_t, dec, s_raw, s_sorted, perm, Dsuf, part, sw);
+        factor<T>(D, w, mw, nw, 0, f_t, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
         if (!(dec.s0 > 0.0) || !isfinite(dec.total)) {
             if (tid == 0) {
                 D.status = EA_EINVAL;

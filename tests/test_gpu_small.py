@@ -22,19 +22,20 @@ def _say(*a):
 
 def _run(prog, prec, f_min, small, kind="pure"):
     with P.EAState(prog.n_sites, kind, prec) as st:
-        st.set_option(P.EA_OPT_SMALL_LAYERS, 1 if small else 0)
+        st.set_option(P.EA_OPT_SMALL_LAYERS, small if small is not True else 64)
         st.run(prog, f_min)
         out = (st.statevector() if kind == "pure" else st.density(), st.fidelity_estimate()[0],
                st.gate_log(), st.bond_dims())
     return out
 
 
-@pytest.mark.parametrize("n,depth,seed", [(14, 12, 11), (11, 9, 12)])
-def test_small_path_fp64_matches_host_path_and_oracle(n, depth, seed):
-    _say("case: small fp64", n, depth, seed)
+@pytest.mark.parametrize("n,depth,seed,cols", [(14, 12, 11, 64), (11, 9, 12, 64),
+                                               (16, 15, 13, 64), (16, 15, 13, 128)])
+def test_small_path_fp64_matches_host_path_and_oracle(n, depth, seed, cols):
+    _say("case: small fp64", n, depth, seed, cols)
     prog = C.brickwork_program(n, depth, seed)
-    psi_s, F_s, log_s, b_s = _run(prog, "c128", 0.97, True)
-    psi_h, F_h, log_h, b_h = _run(prog, "c128", 0.97, False)
+    psi_s, F_s, log_s, b_s = _run(prog, "c128", 0.97, cols)
+    psi_h, F_h, log_h, b_h = _run(prog, "c128", 0.97, 0)
     o = oracle_run(prog, 0.97)
     for g, r in zip(log_s, o.log):
         if protected(r, r.f_t, 1e-12):
@@ -59,11 +60,11 @@ def test_small_path_exact_vs_bruteforce():
 
 def test_small_path_fp32_and_bf16x3():
     prog = C.brickwork_program(12, 8, 21)
-    ref, _, _, _ = _run(prog, "c128", 0.98, False)
+    ref, _, _, _ = _run(prog, "c128", 0.98, 0)
     for prec in ("c64", "bf16x3"):
         _say("case: small", prec)
         psi, F, log, _ = _run(prog, prec, 0.98, True)
-        psi_h, F_h, _, _ = _run(prog, prec, 0.98, False)
+        psi_h, F_h, _, _ = _run(prog, prec, 0.98, 0)
         assert np.abs(psi - ref).max() < 2e-4
         assert abs(F - F_h) < 1e-5
 
@@ -76,7 +77,7 @@ def test_small_path_mpo_vs_bruteforce():
     rng = np.random.default_rng(31)
     gates = []
     with P.EAState(n, "mixed", "c128") as st:
-        st.set_option(P.EA_OPT_SMALL_LAYERS, 1)
+        st.set_option(P.EA_OPT_SMALL_LAYERS, 64)
         for t in range(5):
             pairs = list(C.brickwork_pairs(n, t))
             ops = []
@@ -90,15 +91,17 @@ def test_small_path_mpo_vs_bruteforce():
     np.testing.assert_allclose(rho_g, rho, atol=1e-10)
 
 
-def test_small_batched_many_states_one_launch():
+@pytest.mark.parametrize("cols", [64, 128])
+def test_small_batched_many_states_one_launch(cols):
     """Twenty states of different sizes in one launch per layer, against each
     state run alone on the host-orchestrated path."""
-    _say("case: small batched")
+    _say("case: small batched", cols)
     rng = np.random.default_rng(5)
-    progs = [C.brickwork_program(int(rng.integers(6, 16)), int(rng.integers(3, 9)), 500 + b)
+    progs = [C.brickwork_program(int(rng.integers(6, 16)), int(rng.integers(3, 13)), 500 + b)
              for b in range(20)]
     states = [P.EAState(p.n_sites, "pure", "c128") for p in progs]
     for st, p in zip(states, progs):
+        st.set_option(P.EA_OPT_SMALL_LAYERS, cols)
         st.set_schedule(0.98, p.n_2q)
     depth = max(len(p.layers) for p in progs)
     for t in range(depth):
@@ -113,6 +116,6 @@ def test_small_batched_many_states_one_launch():
         psi = st.statevector()
         ks = [r["k"] for r in st.gate_log()]
         st.close()
-        psi_h, F_h, log_h, _ = _run(p, "c128", 0.98, False)
+        psi_h, F_h, log_h, _ = _run(p, "c128", 0.98, 0)
         assert ks == [r["k"] for r in log_h]
         np.testing.assert_allclose(psi, psi_h, atol=1e-10)
