@@ -159,33 +159,24 @@ def cpu_baseline(prog, f_min, chi_max, n_layers, budget_s):
 
 def bench_batched(args, torch, C, P):
     """Independent circuits of the batched workload (N ~ U{20..80}, depth ~
-    U{10..40}, capped at --max-depth, F_min = 0.99, chi <= 1024), advanced layer
-    by layer together (one stream per state) and, for comparison, one after
-    the other."""
+    U{10..40}, capped at --max-depth, F_min = 0.99, chi <= 1024), advanced
+    together (leading small-bond layers in one device-resident launch, then
+    one batched call per layer) and, for comparison, one after the other."""
     import numpy as np
     progs = C.batched_programs(64)[: args.circuits]
     for p in progs:
         p.layers = p.layers[: args.max_depth]
     n_upd = sum(p.n_2q for p in progs)
 
-    def layer_args(t):
-        sites, ops = [], []
-        for p in progs:
-            layer = p.layers[t] if t < len(p.layers) else []
-            sites.append([op.site for op in layer])
-            ops.append(np.stack([op.mat for op in layer]) if layer else np.zeros((0, 4, 4), complex))
-        return sites, ops
-
     states = [P.EAState(p.n_sites, "pure", args.prec, chi_max=1024) for p in progs]
     depth = max(len(p.layers) for p in progs)
-    largs = [layer_args(t) for t in range(depth)]
 
     def run_batched():
-        for st, p in zip(states, progs):
+        # leading small-bond layers of all circuits in one device-resident
+        # launch, then one batched call per remaining layer
+        for st in states:
             st.reset()
-            st.set_schedule(0.99, p.n_2q)
-        for t in range(depth):
-            P.mps_apply_layer_batched([s.h for s in states], *largs[t])
+        P.run_batched(states, progs, 0.99)
 
     def run_sequential():
         for st, p in zip(states, progs):

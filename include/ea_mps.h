@@ -186,6 +186,28 @@ int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
                             const double *const *budgets, double *const *f_out,
                             int *status_out);
 
+/* Leading layers of many independent circuits in ONE device-resident launch
+ * (Sec. V-VI; the same updates as repeated mps_apply_layer calls with the
+ * schedule of mps_set_schedule, no per-gate targets).  One workgroup per
+ * state walks its layers in order (centre moves, contraction, SVD, kept-rank
+ * rule, write-back, fidelity product) with every size read on the device, and
+ * stops before the first layer at which some bond exceeds the small-layer
+ * limit (EA_OPT_SMALL_LAYERS c: bonds <= c / d; c = 0 runs nothing).  A state
+ * that does not qualify when the call starts is left untouched.
+ *   n_layers[b]       layers offered for state b
+ *   layer_gates[b][L] number of two-qubit gates in layer L of state b
+ *   sites[b]          left sites of all its gates, layer after layer
+ *   ops[b]            their operators, complex d^2 x d^2 row-major each
+ *                     (interleaved re, im doubles), in the same order
+ *   layers_done[b]    out: layers applied; the caller continues from there
+ *                     (for example with mps_apply_layer_batched)
+ *   status_out[b]     out (may be NULL): each state's status
+ * Host arrays are read during the call only.  The states synchronise their
+ * streams first.  Returns the most severe status (errors < warnings). */
+int mps_run_layers_batched(int n_states, ea_mps *const *hs, const int *n_layers,
+                           const int *const *layer_gates, const int *const *sites,
+                           const double *const *ops, int *layers_done, int *status_out);
+
 /* Running estimate of the state fidelity, prod_i f_i (Eq. 12; Eq. 13 for
  * noisy runs, where it is a lower estimate).  Either pointer may be NULL. */
 int mps_fidelity_estimate(const ea_mps *h, double *F_out, double *lnF_out);

@@ -6,4 +6,4 @@ the work; this package binds it (``_binding``) and offers a small driver
 """
 from ._binding import *  # noqa: F401,F403
 from ._binding import SYMBOLS, LIB_PATH, EAError  # noqa: F401
-from .driver import EAState  # noqa: F401
+from .driver import EAState, run_batched  # noqa: F401

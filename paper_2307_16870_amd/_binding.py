@@ -29,7 +29,7 @@ SYMBOLS = [
     "mps_apply_2q", "mps_apply_layer", "mps_fidelity_estimate", "mps_expect",
     "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
-    "mps_apply_layer_batched", "mps_energy_grad", "ea_last_error",
+    "mps_apply_layer_batched", "mps_run_layers_batched", "mps_energy_grad", "ea_last_error",
 ]
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_profile_read": (I, [P, I, dp, ct.POINTER(ct.c_long), dp, dp]),
         "mps_apply_layer_batched": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(dp),
                                         ct.POINTER(dp), ct.POINTER(dp), ip]),
+        "mps_run_layers_batched": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(ip),
+                                       ct.POINTER(dp), ip, ip]),
         "mps_energy_grad": (I, [P, I, ct.POINTER(DOp), dp, I, I, ip, ip, dp, dp, D, D, dp, dp, dp]),
         "ea_last_error": (ct.c_char_p, []),
     }
@@ -287,6 +289,39 @@ def mps_apply_layer_batched(handles, sites_list, ops_list, budgets_list=None):
                                       bp if budgets_list is not None else None, fp, _ip(st))
     _chk(rc)
     return rc, st.tolist(), fs
+
+
+def mps_run_layers_batched(handles, layers_list):
+    """Leading layers of every state in one device-resident launch.
+    ``layers_list[b]`` is a list of layers, each a list of (site, 4x4 or 16x16
+    operator).  Returns (worst status, per-state statuses, per-state number
+    of layers applied)."""
+    nb = len(handles)
+    hs = (ct.c_void_p * nb)(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
+    keep = []
+    nl = np.ascontiguousarray([len(L) for L in layers_list], dtype=np.int32)
+    gp = (ct.POINTER(ct.c_int) * nb)()
+    sp = (ct.POINTER(ct.c_int) * nb)()
+    op = (ct.POINTER(ct.c_double) * nb)()
+    for b in range(nb):
+        counts = np.ascontiguousarray([len(layer) for layer in layers_list[b]], dtype=np.int32)
+        sites = np.ascontiguousarray([g[0] for layer in layers_list[b] for g in layer],
+                                     dtype=np.int32)
+        mats = [np.asarray(g[1], dtype=np.complex128) for layer in layers_list[b] for g in layer]
+        o = _c(np.stack(mats)) if mats else _c(np.zeros((1, 4, 4), complex))
+        if sites.size == 0:
+            sites = np.zeros(1, dtype=np.int32)
+        if counts.size == 0:
+            counts = np.zeros(1, dtype=np.int32)
+        keep += [counts, sites, o]
+        gp[b] = _ip(counts)
+        sp[b] = _ip(sites)
+        op[b] = _dp(o)
+    done = np.zeros(nb, dtype=np.int32)
+    st = np.zeros(nb, dtype=np.int32)
+    rc = _lib.mps_run_layers_batched(nb, hs, _ip(nl), gp, sp, op, _ip(done), _ip(st))
+    _chk(rc)
+    return rc, st.tolist(), done.tolist()
 
 
 def make_dops(ops):

@@ -103,7 +103,7 @@ void mps_free(ea_mps *h) {
     for (auto &b : h->site) free_buf(b);
     DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
-                      &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_gsite,
+                      &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_loff, &h->sm_gsite,
                       &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs};
     for (DevBuf *b : bufs) free_buf(*b);
     if (h->stage_host) (void)hipHostFree(h->stage_host);
@@ -239,11 +239,22 @@ bool small_eligible(const ea_mps *h, int n_gates) {
     return true;
 }
 
-// Upload one state's layer and fill its descriptor (host copy).
+// One state's share of a device-resident launch: consecutive layers of
+// two-qubit gates (layer L holds gates off[L] .. off[L+1]-1).
+struct SmallJob {
+    int b = 0;                       // index of the state in the caller's arrays
+    std::vector<int> off;            // n_layers + 1 gate offsets
+    const int *sites = nullptr;      // all gates' left sites
+    const double *ops = nullptr;     // all gates' operators (complex d^4 each)
+    const double *budgets = nullptr; // per gate, single-layer calls only
+    double *f_out = nullptr;         // per gate, single-layer calls only
+    int layers_done = 0;
+};
+
+// Upload one state's layers and fill its descriptor (host copy).
 template <typename T>
-int small_prepare(ea_mps *h, int n_gates, const int *sites, const double *ops,
-                  const double *budgets, bool want_f, SmallDesc<T> &D) {
-    const int d = h->d;
+int small_prepare(ea_mps *h, const SmallJob &job, SmallDesc<T> &D) {
+    const int d = h->d, n_layers = (int)job.off.size() - 1, total = job.off.back();
     const size_t cap = SM_ELEMS;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     for (int i = 0; i < h->n; ++i) {  // grow the site buffers, keeping their tensors
@@ -256,36 +267,42 @@ int small_prepare(ea_mps *h, int n_gates, const int *sites, const double *ops,
         free_buf(h->site[i]);
         h->site[i] = nb;
     }
+    const size_t nop = (size_t)d * d * d * d;
     TRY(ensure(h, h->sm_scratch, small_scratch_bytes(h->csz)));
     TRY(ensure(h, h->sm_sites, sizeof(void *) * h->n));
     TRY(ensure(h, h->sm_bond, sizeof(int) * (h->n + 1)));
-    TRY(ensure(h, h->sm_gsite, sizeof(int) * SM_GATES));
-    TRY(ensure(h, h->sm_gmat, h->csz * (size_t)SM_GATES * d * d * d * d));
-    TRY(ensure(h, h->sm_budget, sizeof(double) * SM_GATES));
-    TRY(ensure(h, h->sm_log, sizeof(ea_gate_record) * SM_GATES));
-    TRY(ensure(h, h->sm_fout, sizeof(double) * SM_GATES));
+    TRY(ensure(h, h->sm_loff, sizeof(int) * (n_layers + 1)));
+    TRY(ensure(h, h->sm_gsite, sizeof(int) * std::max(1, total)));
+    TRY(ensure(h, h->sm_gmat, h->csz * nop * std::max(1, total)));
+    TRY(ensure(h, h->sm_budget, sizeof(double) * std::max(1, total)));
+    TRY(ensure(h, h->sm_log, sizeof(ea_gate_record) * std::max(1, total)));
+    TRY(ensure(h, h->sm_fout, sizeof(double) * std::max(1, total)));
     std::vector<void *> ptrs(h->n);
     for (int i = 0; i < h->n; ++i) ptrs[i] = h->site[i].p;
-    const size_t nop = (size_t)d * d * d * d;
-    std::vector<T> g(2 * nop * n_gates);
-    for (size_t e = 0; e < g.size(); ++e) g[e] = (T)ops[e];
+    std::vector<T> g(2 * nop * total);
+    for (size_t e = 0; e < g.size(); ++e) g[e] = (T)job.ops[e];
     HIPCHK(h, hipMemcpy(h->sm_sites.p, ptrs.data(), sizeof(void *) * h->n, hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->sm_bond.p, h->bond.data(), sizeof(int) * (h->n + 1),
                         hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(h->sm_gsite.p, sites, sizeof(int) * n_gates, hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(h->sm_gmat.p, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice));
-    if (budgets)
-        HIPCHK(h, hipMemcpy(h->sm_budget.p, budgets, sizeof(double) * n_gates,
+    HIPCHK(h, hipMemcpy(h->sm_loff.p, job.off.data(), sizeof(int) * (n_layers + 1),
+                        hipMemcpyHostToDevice));
+    if (total > 0) {
+        HIPCHK(h, hipMemcpy(h->sm_gsite.p, job.sites, sizeof(int) * total, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->sm_gmat.p, g.data(), sizeof(T) * g.size(), hipMemcpyHostToDevice));
+    }
+    if (job.budgets)
+        HIPCHK(h, hipMemcpy(h->sm_budget.p, job.budgets, sizeof(double) * total,
                             hipMemcpyHostToDevice));
     D = SmallDesc<T>{};
     D.site = (cx<T> *const *)h->sm_sites.p;
     D.bond = (int *)h->sm_bond.p;
     D.scratch = (cx<T> *)h->sm_scratch.p;
+    D.layer_off = (const int *)h->sm_loff.p;
     D.gsite = (const int *)h->sm_gsite.p;
     D.gmat = (const cx<T> *)h->sm_gmat.p;
-    D.budget = budgets ? (const double *)h->sm_budget.p : nullptr;
+    D.budget = job.budgets ? (const double *)h->sm_budget.p : nullptr;
     D.log = (ea_gate_record *)h->sm_log.p;
-    D.fout = want_f ? (double *)h->sm_fout.p : nullptr;
+    D.fout = job.f_out ? (double *)h->sm_fout.p : nullptr;
     D.tau = h->tau;
     D.tol_user = h->tol;
     D.f_min = h->f_min;
@@ -296,7 +313,9 @@ int small_prepare(ea_mps *h, int n_gates, const int *sites, const double *ops,
     D.n = h->n;
     D.d = d;
     D.kind = h->kind;
-    D.n_gates = n_gates;
+    D.n_gates = total;
+    D.n_layers = n_layers;
+    D.lim = h->small_cols / d;
     D.center = h->center;
     D.chi_max = h->chi_max;
     D.max_sweeps = h->max_sweeps;
@@ -307,23 +326,24 @@ int small_prepare(ea_mps *h, int n_gates, const int *sites, const double *ops,
     return EA_OK;
 }
 
-// Read back one state's layer; returns its status.
+// Read back one state; returns its status.
 template <typename T>
-int small_finish(ea_mps *h, const SmallDesc<T> &D, double *f_out) {
+int small_finish(ea_mps *h, const SmallDesc<T> &D, SmallJob &job) {
     HIPCHK(h, hipMemcpy(h->bond.data(), h->sm_bond.p, sizeof(int) * (h->n + 1),
                         hipMemcpyDeviceToHost));
     std::vector<ea_gate_record> recs(D.n_done);
     if (D.n_done > 0)
         HIPCHK(h, hipMemcpy(recs.data(), h->sm_log.p, sizeof(ea_gate_record) * D.n_done,
                             hipMemcpyDeviceToHost));
-    if (f_out && D.n_gates > 0)
-        HIPCHK(h, hipMemcpy(f_out, h->sm_fout.p, sizeof(double) * D.n_gates,
+    if (job.f_out && D.n_gates > 0)
+        HIPCHK(h, hipMemcpy(job.f_out, h->sm_fout.p, sizeof(double) * D.n_gates,
                             hipMemcpyDeviceToHost));
     for (auto &r : recs) h->log.push_back(r);
     h->center = D.center;
     h->lnP = D.lnP;
     h->lnS = D.lnS;
     h->g = D.g;
+    job.layers_done = D.layers_done;
     if (D.status < 0)
         return set_err(D.status, "the operator annihilates the state (all singular values 0)");
     int rc = EA_OK;
@@ -332,40 +352,30 @@ int small_finish(ea_mps *h, const SmallDesc<T> &D, double *f_out) {
     return rc;
 }
 
-// All eligible states of one precision in one launch (one workgroup each).
+// All jobs of one precision in one launch (one workgroup per state).
 template <typename T>
-void small_batch(const std::vector<int> &idx, ea_mps *const *hs, const int *n_gates,
-                 const int *const *sites, const double *const *ops,
-                 const double *const *budgets, double *const *f_out, std::vector<int> &rc,
+void small_batch(std::vector<SmallJob> &jobs, ea_mps *const *hs, std::vector<int> &rc,
                  std::vector<std::string> &err) {
-    if (idx.empty()) return;
-    std::vector<SmallDesc<T>> descs(idx.size());
-    std::vector<int> ok(idx.size(), 0);
-    for (size_t u = 0; u < idx.size(); ++u) {
-        const int b = idx[u];
-        const int r = small_prepare<T>(hs[b], n_gates[b], sites[b], ops[b],
-                                       budgets ? budgets[b] : nullptr, f_out && f_out[b],
-                                       descs[u]);
-        if (r < 0) {
-            rc[b] = r;
-            err[b] = g_err;
-        } else {
-            ok[u] = 1;
-        }
-    }
+    if (jobs.empty()) return;
     std::vector<SmallDesc<T>> run;
     std::vector<int> run_u;
-    for (size_t u = 0; u < idx.size(); ++u)
-        if (ok[u]) {
-            run.push_back(descs[u]);
+    for (size_t u = 0; u < jobs.size(); ++u) {
+        SmallDesc<T> D;
+        const int r = small_prepare<T>(hs[jobs[u].b], jobs[u], D);
+        if (r < 0) {
+            rc[jobs[u].b] = r;
+            err[jobs[u].b] = g_err;
+        } else {
+            run.push_back(D);
             run_u.push_back((int)u);
         }
+    }
     if (run.empty()) return;
-    ea_mps *h0 = hs[idx[run_u[0]]];
+    ea_mps *h0 = hs[jobs[run_u[0]].b];
     auto fail_all = [&](int r) {
         for (int u : run_u) {
-            rc[idx[u]] = r;
-            err[idx[u]] = g_err;
+            rc[jobs[u].b] = r;
+            err[jobs[u].b] = g_err;
         }
     };
     int r = ensure(h0, h0->sm_descs, sizeof(SmallDesc<T>) * run.size());
@@ -381,9 +391,9 @@ void small_batch(const std::vector<int> &idx, ea_mps *const *hs, const int *n_ga
                   hipMemcpyDeviceToHost) != hipSuccess)
         return fail_all(set_err(EA_EHIP, "descriptor read-back failed"));
     for (size_t v = 0; v < run.size(); ++v) {
-        const int b = idx[run_u[v]];
-        rc[b] = small_finish<T>(hs[b], run[v], f_out ? f_out[b] : nullptr);
-        if (rc[b] != EA_OK) err[b] = g_err;
+        SmallJob &job = jobs[run_u[v]];
+        rc[job.b] = small_finish<T>(hs[job.b], run[v], job);
+        if (rc[job.b] != EA_OK) err[job.b] = g_err;
     }
 }
 }  // namespace
@@ -396,18 +406,19 @@ int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
     TRY(validate_layer(h, n_gates, sites, ops, budgets, &lo, &hi));
     if (n_gates == 0) return EA_OK;
     if (small_eligible(h, n_gates)) {  // the whole layer in one device-resident launch
-        std::vector<int> idx{0}, rc1(1, EA_OK);
+        std::vector<SmallJob> jobs(1);
+        jobs[0].off = {0, n_gates};
+        jobs[0].sites = sites;
+        jobs[0].ops = ops;
+        jobs[0].budgets = budgets;
+        jobs[0].f_out = f_out;
+        std::vector<int> rc1(1, EA_OK);
         std::vector<std::string> err1(1);
         ea_mps *hs1[1] = {h};
-        const int ng1[1] = {n_gates};
-        const int *s1[1] = {sites};
-        const double *o1[1] = {ops};
-        const double *b1[1] = {budgets};
-        double *f1[1] = {f_out};
         if (h->f64)
-            small_batch<double>(idx, hs1, ng1, s1, o1, b1, f1, rc1, err1);
+            small_batch<double>(jobs, hs1, rc1, err1);
         else
-            small_batch<float>(idx, hs1, ng1, s1, o1, b1, f1, rc1, err1);
+            small_batch<float>(jobs, hs1, rc1, err1);
         if (rc1[0] != EA_OK) g_err = err1[0];
         return rc1[0];
     }
@@ -448,7 +459,8 @@ int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
     std::vector<std::string> err(n_states);
     // states whose bonds are all small: one device-resident launch per
     // precision; the others: one host thread and stream each
-    std::vector<int> small32, small64, big;
+    std::vector<SmallJob> small32, small64;
+    std::vector<int> big;
     for (int b = 0; b < n_states; ++b) {
         if (n_gates[b] > 0 && small_eligible(hs[b], n_gates[b])) {
             int r = validate_layer(hs[b], n_gates[b], sites[b], ops[b],
@@ -458,7 +470,14 @@ int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
                 err[b] = g_err;
                 continue;
             }
-            (hs[b]->f64 ? small64 : small32).push_back(b);
+            SmallJob job;
+            job.b = b;
+            job.off = {0, n_gates[b]};
+            job.sites = sites[b];
+            job.ops = ops[b];
+            job.budgets = budgets ? budgets[b] : nullptr;
+            job.f_out = f_out ? f_out[b] : nullptr;
+            (hs[b]->f64 ? small64 : small32).push_back(job);
         } else {
             big.push_back(b);
         }
@@ -471,10 +490,69 @@ int mps_apply_layer_batched(int n_states, ea_mps *const *hs, const int *n_gates,
     std::vector<std::thread> pool;
     pool.reserve(big.size());
     for (size_t u = 1; u < big.size(); ++u) pool.emplace_back(work, big[u]);
-    small_batch<float>(small32, hs, n_gates, sites, ops, budgets, f_out, rc, err);
-    small_batch<double>(small64, hs, n_gates, sites, ops, budgets, f_out, rc, err);
+    small_batch<float>(small32, hs, rc, err);
+    small_batch<double>(small64, hs, rc, err);
     if (!big.empty()) work(big[0]);
     for (auto &t : pool) t.join();
+    int worst = EA_OK, worst_b = -1;
+    for (int b = 0; b < n_states; ++b) {
+        if (status_out) status_out[b] = rc[b];
+        if ((rc[b] < 0 && (worst >= 0 || rc[b] < worst)) || (worst >= 0 && rc[b] > worst)) {
+            worst = rc[b];
+            worst_b = b;
+        }
+    }
+    if (worst_b >= 0) set_err(worst, "state %d: %s", worst_b, err[worst_b].c_str());
+    return worst;
+}
+
+int mps_run_layers_batched(int n_states, ea_mps *const *hs, const int *n_layers,
+                           const int *const *layer_gates, const int *const *sites,
+                           const double *const *ops, int *layers_done, int *status_out) {
+    if (n_states < 0) return set_err(EA_EINVAL, "n_states < 0");
+    if (n_states == 0) return EA_OK;
+    if (!hs || !n_layers || !layer_gates || !sites || !ops || !layers_done)
+        return set_err(EA_EINVAL, "null argument");
+    for (int b = 0; b < n_states; ++b) {
+        TRY(check(hs[b]));
+        for (int c = 0; c < b; ++c)
+            if (hs[c] == hs[b]) return set_err(EA_EINVAL, "a state appears twice in the batch");
+        if (n_layers[b] < 0) return set_err(EA_EINVAL, "n_layers < 0");
+    }
+    std::vector<int> rc(n_states, EA_OK);
+    std::vector<std::string> err(n_states);
+    std::vector<SmallJob> small32, small64;
+    for (int b = 0; b < n_states; ++b) {
+        layers_done[b] = 0;
+        ea_mps *h = hs[b];
+        const size_t nop = (size_t)h->d * h->d * h->d * h->d;
+        SmallJob job;
+        job.b = b;
+        job.off.assign(1, 0);
+        int maxg = 0, r = EA_OK;
+        for (int L = 0; L < n_layers[b] && r == EA_OK; ++L) {
+            const int ng = layer_gates[b][L];
+            if (ng < 0) r = set_err(EA_EINVAL, "negative gate count in layer %d", L);
+            else
+                r = validate_layer(h, ng, sites[b] + job.off.back(), ops[b] + 2 * nop * job.off.back(),
+                                   nullptr, nullptr, nullptr);
+            maxg = std::max(maxg, ng);
+            job.off.push_back(job.off.back() + std::max(0, ng));
+        }
+        if (r < 0) {
+            rc[b] = r;
+            err[b] = g_err;
+            continue;
+        }
+        if (n_layers[b] == 0 || !small_eligible(h, std::max(1, maxg)) || maxg > SM_GATES) continue;
+        job.sites = sites[b];
+        job.ops = ops[b];
+        (h->f64 ? small64 : small32).push_back(job);
+    }
+    small_batch<float>(small32, hs, rc, err);
+    small_batch<double>(small64, hs, rc, err);
+    for (auto *jobs : {&small32, &small64})
+        for (auto &j : *jobs) layers_done[j.b] = j.layers_done;
     int worst = EA_OK, worst_b = -1;
     for (int b = 0; b < n_states; ++b) {
         if (status_out) status_out[b] = rc[b];

@@ -63,8 +63,8 @@ struct ea_mps {
     int jorder = 1;  // 1: pairs inside a column block rotated in a sweep's first round only
     ea::DevBuf W, V, X, X2, s_raw, s_sorted, perm, rec, ints, partial, envb, tmp, out3, c128;
     // device-resident small-bond layers
-    ea::DevBuf sm_scratch, sm_sites, sm_bond, sm_gsite, sm_gmat, sm_budget, sm_log, sm_fout,
-        sm_descs;
+    ea::DevBuf sm_scratch, sm_sites, sm_bond, sm_loff, sm_gsite, sm_gmat, sm_budget, sm_log,
+        sm_fout, sm_descs;
     int small_cols = 64;  // device-resident layers: largest factorisation width (0: off)
     ea_dev_rec *rec_host = nullptr;
     int *int_host = nullptr;

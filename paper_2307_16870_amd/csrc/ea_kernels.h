@@ -178,22 +178,23 @@ constexpr int SM_GATES = 256;  // gates of one state's layer
 // complex FP64 Gram.
 constexpr size_t SM_ELEMS = (size_t)SM_N * SM_N;
 inline size_t small_scratch_bytes(size_t csz) { return csz * 6 * SM_ELEMS + 16 * SM_ELEMS; }
-// One state of a small-bond layer; read and updated by its workgroup.
+// One state's consecutive small-bond layers; read and updated by its workgroup.
 template <typename T>
 struct SmallDesc {
     cx<T> *const *site;    // device array of n site pointers
     int *bond;             // device, n + 1 bond dimensions
     cx<T> *scratch;        // small_scratch_bytes
-    const int *gsite;      // left sites of this layer's gates (caller's order)
+    const int *layer_off;  // n_layers + 1 offsets into the gate arrays
+    const int *gsite;      // left sites of the gates (caller's order within a layer)
     const cx<T> *gmat;     // d^4 complex per gate
     const double *budget;  // per-gate target (< 0: schedule), or null
     ea_gate_record *log;   // one record per gate, in visiting order
     double *fout;          // per-gate f (caller's order), or null
     double tau, tol_user, f_min, lnP, lnS;
     long long n_total, g;
-    int n, d, kind, n_gates, center, asc;
+    int n, d, kind, n_gates, n_layers, lim, center, asc;  // lim: largest bond for a layer
     int chi_max, max_sweeps, inner, has_sched, strategy, reorth;
-    int status, n_capped, n_noconv, n_done;
+    int status, n_capped, n_noconv, n_done, layers_done;
 };
 template <typename T>
 void launch_layer_small(SmallDesc<T> *descs, int n_states, hipStream_t s);

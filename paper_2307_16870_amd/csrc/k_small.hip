@@ -275,195 +275,209 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
     __shared__ Dec dec;
     __shared__ double s_raw[SM_N], s_sorted[SM_N], Dsuf[SM_N + 1], part[NTH];
     __shared__ int perm[SM_N], order[SM_GATES], sw[2], cnt[1];
-    __shared__ int center_sh, stop_sh;
-    const int tid = threadIdx.x, d = D.d, ng = D.n_gates;
+    __shared__ int center_sh, big_sh;
+    const int tid = threadIdx.x, d = D.d;
     int *bond = D.bond;
     cx<T> *const *site = D.site;
-    if (tid == 0) {
-        int lo = D.n, hi = -1;
-        for (int j = 0; j < ng; ++j) {
-            lo = min(lo, D.gsite[j]);
-            hi = max(hi, D.gsite[j]);
-            order[j] = j;
-        }
-        const bool asc = abs(D.center - lo) <= abs(D.center - hi);
-        for (int a = 1; a < ng; ++a) {  // insertion sort by site
-            const int v = order[a];
-            int b = a - 1;
-            while (b >= 0 && (asc ? D.gsite[order[b]] > D.gsite[v] : D.gsite[order[b]] < D.gsite[v])) {
-                order[b + 1] = order[b];
-                --b;
-            }
-            order[b + 1] = v;
-        }
-        D.asc = asc ? 1 : 0;
-        center_sh = D.center;
-        stop_sh = 0;
-    }
+    if (tid == 0) center_sh = D.center;
     __syncthreads();
-    const int asc = D.asc;
-    for (int gi = 0; gi < ng; ++gi) {
-        const int j = order[gi], i = D.gsite[j];
-        // ---- centre moves (Sec. III) ----
-        while (true) {
-            const int c = center_sh;
-            const int dir = c < i ? 1 : (c > i + 1 ? -1 : 0);
-            if (dir == 0) break;
-            if (dir > 0) {  // A_c = U (S V^H): A_c <- U, A_{c+1} <- (S V^H) A_{c+1}
-                const int M = bond[c] * d, N = bond[c + 1];
-                const int orient = M >= N ? 0 : 1, mw = max(M, N), nw = min(M, N);
-                for (int e = tid; e < M * N; e += NTH) {
-                    const int r = e / N, cc = e % N;
-                    const cx<T> v = site[c][e];
-                    if (orient == 0) w.W[(size_t)cc * M + r] = v;
-                    else w.W[e] = conj(v);
+    for (int L = 0; L < D.n_layers; ++L) {
+        // a later layer runs here only while every bond is within the limit
+        if (tid == 0) big_sh = 0;
+        __syncthreads();
+        for (int x = tid; x <= D.n; x += NTH)
+            if (bond[x] > D.lim) big_sh = 1;
+        __syncthreads();
+        if (big_sh) break;
+        const int g0 = D.layer_off[L], ng = D.layer_off[L + 1] - g0;
+        if (tid == 0) {
+            int lo = D.n, hi = -1;
+            for (int j = 0; j < ng; ++j) {
+                lo = min(lo, D.gsite[g0 + j]);
+                hi = max(hi, D.gsite[g0 + j]);
+                order[j] = g0 + j;
+            }
+            const bool asc = abs(center_sh - lo) <= abs(center_sh - hi);
+            for (int a = 1; a < ng; ++a) {  // insertion sort by site
+                const int v = order[a];
+                int b = a - 1;
+                while (b >= 0 &&
+                       (asc ? D.gsite[order[b]] > D.gsite[v] : D.gsite[order[b]] < D.gsite[v])) {
+                    order[b + 1] = order[b];
+                    --b;
                 }
-                __syncthreads();
-                factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
-                if (!(dec.s0 > 0.0)) {
-                    if (tid == 0) {
-                        D.status = EA_EINVAL;
-                        D.center = center_sh;
+                order[b + 1] = v;
+            }
+            D.asc = asc ? 1 : 0;
+        }
+        __syncthreads();
+        const int asc = D.asc;
+        for (int gi = 0; gi < ng; ++gi) {
+            const int j = order[gi], i = D.gsite[j];
+            // ---- centre moves (Sec. III) ----
+            while (true) {
+                const int c = center_sh;
+                const int dir = c < i ? 1 : (c > i + 1 ? -1 : 0);
+                if (dir == 0) break;
+                if (dir > 0) {  // A_c = U (S V^H): A_c <- U, A_{c+1} <- (S V^H) A_{c+1}
+                    const int M = bond[c] * d, N = bond[c + 1];
+                    const int orient = M >= N ? 0 : 1, mw = max(M, N), nw = min(M, N);
+                    for (int e = tid; e < M * N; e += NTH) {
+                        const int r = e / N, cc = e % N;
+                        const cx<T> v = site[c][e];
+                        if (orient == 0) w.W[(size_t)cc * M + r] = v;
+                        else w.W[e] = conj(v);
                     }
-                    return;
-                }
-                const int k = dec.k, chi2 = bond[c + 2];
-                if (orient == 0) {
-                    gather<T>(w.W, M, perm, s_sorted, dec, k, M, 0, -1, 0, 1, site[c]);
-                    gather<T>(w.V, N, perm, s_sorted, dec, k, N, 1, 1, 0, 0, w.X);
-                } else {
-                    gather<T>(w.V, M, perm, s_sorted, dec, k, M, 0, 0, 0, 1, site[c]);
-                    gather<T>(w.W, N, perm, s_sorted, dec, k, N, 1, 0, 0, 0, w.X);
-                }
-                __syncthreads();
-                gemm_copy<T>(w.X, site[c + 1], w.P, site[c + 1], k, d * chi2, N);
-                if constexpr (sizeof(T) == 4)
-                    if (D.reorth) reorth<T>(w, true, site[c], M, k, site[c + 1], d * chi2);
-                if (tid == 0) {
-                    bond[c + 1] = k;
-                    center_sh = c + 1;
-                }
-            } else {  // A_c = (U S) V^H: A_c <- V^H, A_{c-1} <- A_{c-1} (U S)
-                const int M = bond[c], N = d * bond[c + 1];
-                const int orient = M >= N ? 0 : 1, mw = max(M, N), nw = min(M, N);
-                for (int e = tid; e < M * N; e += NTH) {
-                    const int r = e / N, cc = e % N;
-                    const cx<T> v = site[c][e];
-                    if (orient == 0) w.W[(size_t)cc * M + r] = v;
-                    else w.W[e] = conj(v);
-                }
-                __syncthreads();
-                factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
-                if (!(dec.s0 > 0.0)) {
-                    if (tid == 0) {
-                        D.status = EA_EINVAL;
-                        D.center = center_sh;
+                    __syncthreads();
+                    factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
+                    if (!(dec.s0 > 0.0)) {
+                        if (tid == 0) {
+                            D.status = EA_EINVAL;
+                            D.center = center_sh;
+                        }
+                        return;
                     }
-                    return;
-                }
-                const int k = dec.k, rowsP = bond[c - 1] * d;
-                if (orient == 0) {
-                    gather<T>(w.V, N, perm, s_sorted, dec, k, N, 1, 0, 0, 0, site[c]);
-                    gather<T>(w.W, M, perm, s_sorted, dec, k, M, 0, 0, 0, 1, w.X);
-                } else {
-                    gather<T>(w.W, N, perm, s_sorted, dec, k, N, 1, -1, 0, 0, site[c]);
-                    gather<T>(w.V, M, perm, s_sorted, dec, k, M, 0, 1, 0, 1, w.X);
+                    const int k = dec.k, chi2 = bond[c + 2];
+                    if (orient == 0) {
+                        gather<T>(w.W, M, perm, s_sorted, dec, k, M, 0, -1, 0, 1, site[c]);
+                        gather<T>(w.V, N, perm, s_sorted, dec, k, N, 1, 1, 0, 0, w.X);
+                    } else {
+                        gather<T>(w.V, M, perm, s_sorted, dec, k, M, 0, 0, 0, 1, site[c]);
+                        gather<T>(w.W, N, perm, s_sorted, dec, k, N, 1, 0, 0, 0, w.X);
+                    }
+                    __syncthreads();
+                    gemm_copy<T>(w.X, site[c + 1], w.P, site[c + 1], k, d * chi2, N);
+                    if constexpr (sizeof(T) == 4)
+                        if (D.reorth) reorth<T>(w, true, site[c], M, k, site[c + 1], d * chi2);
+                    if (tid == 0) {
+                        bond[c + 1] = k;
+                        center_sh = c + 1;
+                    }
+                } else {  // A_c = (U S) V^H: A_c <- V^H, A_{c-1} <- A_{c-1} (U S)
+                    const int M = bond[c], N = d * bond[c + 1];
+                    const int orient = M >= N ? 0 : 1, mw = max(M, N), nw = min(M, N);
+                    for (int e = tid; e < M * N; e += NTH) {
+                        const int r = e / N, cc = e % N;
+                        const cx<T> v = site[c][e];
+                        if (orient == 0) w.W[(size_t)cc * M + r] = v;
+                        else w.W[e] = conj(v);
+                    }
+                    __syncthreads();
+                    factor<T>(D, w, mw, nw, 1, 1.0, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
+                    if (!(dec.s0 > 0.0)) {
+                        if (tid == 0) {
+                            D.status = EA_EINVAL;
+                            D.center = center_sh;
+                        }
+                        return;
+                    }
+                    const int k = dec.k, rowsP = bond[c - 1] * d;
+                    if (orient == 0) {
+                        gather<T>(w.V, N, perm, s_sorted, dec, k, N, 1, 0, 0, 0, site[c]);
+                        gather<T>(w.W, M, perm, s_sorted, dec, k, M, 0, 0, 0, 1, w.X);
+                    } else {
+                        gather<T>(w.W, N, perm, s_sorted, dec, k, N, 1, -1, 0, 0, site[c]);
+                        gather<T>(w.V, M, perm, s_sorted, dec, k, M, 0, 1, 0, 1, w.X);
+                    }
+                    __syncthreads();
+                    gemm_copy<T>(site[c - 1], w.X, w.P, site[c - 1], rowsP, k, M);
+                    if constexpr (sizeof(T) == 4)
+                        if (D.reorth) reorth<T>(w, false, site[c], N, k, site[c - 1], rowsP);
+                    if (tid == 0) {
+                        bond[c] = k;
+                        center_sh = c - 1;
+                    }
                 }
                 __syncthreads();
-                gemm_copy<T>(site[c - 1], w.X, w.P, site[c - 1], rowsP, k, M);
-                if constexpr (sizeof(T) == 4)
-                    if (D.reorth) reorth<T>(w, false, site[c], N, k, site[c - 1], rowsP);
+            }
+            // ---- two-site update (Sec. V-VI) ----
+            const double b = D.budget ? D.budget[j] : -1.0;
+            double f_t = b >= 0 ? b : schedule_target_dev(D.has_sched, D.strategy, D.f_min, D.n_total, D.g, D.lnP);
+            f_t = fmin(1.0, fmax(f_t, 1e-300));
+            const int chiL = bond[i], chiM = bond[i + 1], chiR = bond[i + 2];
+            const int M = d * chiL, N = d * chiR;
+            const int orient = M >= N ? 0 : 1, mw = max(M, N), nw = min(M, N);
+            const cx<T> *G = D.gmat + (size_t)j * d * d * d * d;
+            // C[(l,t1),(t2,r)] = sum_m A_i[l,t1,m] A_{i+1}[m,t2,r] into P, then the gate
+            for (int e = tid; e < M * N; e += NTH) {
+                const int row = e / N, col = e % N;
+                const int l = row / d, t1 = row % d, t2 = col / chiR, r = col % chiR;
+                cx<T> acc = zero_cx<T>();
+                const cx<T> *a = site[i] + ((size_t)l * d + t1) * chiM;
+                const cx<T> *bb = site[i + 1] + (size_t)t2 * chiR + r;
+                for (int mm = 0; mm < chiM; ++mm) cmac(acc, a[mm], bb[(size_t)mm * d * chiR]);
+                w.P[e] = acc;
+            }
+            __syncthreads();
+            for (int e = tid; e < M * N; e += NTH) {
+                const int row = e / N, col = e % N;
+                const int l = row / d, s1 = row % d, s2 = col / chiR, r = col % chiR;
+                cx<T> th = zero_cx<T>();
+                for (int t1 = 0; t1 < d; ++t1)
+                    for (int t2 = 0; t2 < d; ++t2)
+                        cmac(th, G[(s1 * d + s2) * d * d + t1 * d + t2],
+                             w.P[((size_t)l * d + t1) * N + (size_t)t2 * chiR + r]);
+                if (orient == 0)
+                    w.W[(size_t)col * M + row] = th;
+                else
+                    w.W[(size_t)row * N + col] = conj(th);
+            }
+            __syncthreads();
+            factor<T>(D, w, mw, nw, 0, f_t, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
+            if (!(dec.s0 > 0.0) || !isfinite(dec.total)) {
                 if (tid == 0) {
-                    bond[c] = k;
-                    center_sh = c - 1;
+                    D.status = EA_EINVAL;
+                    D.center = center_sh;
                 }
+                return;
+            }
+            const int k = dec.k;
+            const bool right = asc != 0;
+            if (orient == 0) {
+                gather<T>(w.W, M, perm, s_sorted, dec, k, M, 0, right ? -1 : 0, right ? 0 : 1, 1, site[i]);
+                gather<T>(w.V, N, perm, s_sorted, dec, k, N, 1, right ? 1 : 0, right ? 1 : 0, 0, site[i + 1]);
+            } else {
+                gather<T>(w.V, M, perm, s_sorted, dec, k, M, 0, right ? 0 : 1, right ? 0 : 1, 1, site[i]);
+                gather<T>(w.W, N, perm, s_sorted, dec, k, N, 1, right ? 0 : -1, right ? 1 : 0, 0, site[i + 1]);
+            }
+            __syncthreads();
+            if constexpr (sizeof(T) == 4) {
+                if (D.reorth) {
+                    if (right)
+                        reorth<T>(w, true, site[i], M, k, site[i + 1], N);
+                    else
+                        reorth<T>(w, false, site[i + 1], N, k, site[i], M);
+                }
+            }
+            if (tid == 0) {
+                bond[i + 1] = k;
+                center_sh = right ? i + 1 : i;
+                D.lnP += dec.lnf;
+                if (D.kind == EA_MIXED && dec.kept2 > 0) D.lnS += 0.5 * log(dec.kept2);
+                ea_gate_record &r = D.log[D.n_done];
+                r.gate = D.g;
+                r.site = i;
+                r.chi_l = chiL;
+                r.chi_m = chiM;
+                r.chi_r = chiR;
+                r.k = k;
+                r.k_f = dec.k_f;
+                r.sweeps = dec.sweeps;
+                r.capped = dec.capped;
+                r.f_t = f_t;
+                r.f = dec.f;
+                r.total = dec.total;
+                r.lnP = D.lnP;
+                D.g += 1;
+                if (D.fout) D.fout[j] = dec.f;
+                D.n_capped += dec.capped;
+                D.n_noconv += dec.converged ? 0 : 1;
+                D.n_done += 1;
             }
             __syncthreads();
         }
-        // ---- two-site update (Sec. V-VI) ----
-        const double b = D.budget ? D.budget[j] : -1.0;
-        double f_t = b >= 0 ? b : schedule_target_dev(D.has_sched, D.strategy, D.f_min, D.n_total, D.g, D.lnP);
-        f_t = fmin(1.0, fmax(f_t, 1e-300));
-        const int chiL = bond[i], chiM = bond[i + 1], chiR = bond[i + 2];
-        const int M = d * chiL, N = d * chiR;
-        const int orient = M >= N ? 0 : 1, mw = max(M, N), nw = min(M, N);
-        const cx<T> *G = D.gmat + (size_t)j * d * d * d * d;
-        // C[(l,t1),(t2,r)] = sum_m A_i[l,t1,m] A_{i+1}[m,t2,r] into P, then the gate
-        for (int e = tid; e < M * N; e += NTH) {
-            const int row = e / N, col = e % N;
-            const int l = row / d, t1 = row % d, t2 = col / chiR, r = col % chiR;
-            cx<T> acc = zero_cx<T>();
-            const cx<T> *a = site[i] + ((size_t)l * d + t1) * chiM;
-            const cx<T> *bb = site[i + 1] + (size_t)t2 * chiR + r;
-            for (int mm = 0; mm < chiM; ++mm) cmac(acc, a[mm], bb[(size_t)mm * d * chiR]);
-            w.P[e] = acc;
-        }
-        __syncthreads();
-        for (int e = tid; e < M * N; e += NTH) {
-            const int row = e / N, col = e % N;
-            const int l = row / d, s1 = row % d, s2 = col / chiR, r = col % chiR;
-            cx<T> th = zero_cx<T>();
-            for (int t1 = 0; t1 < d; ++t1)
-                for (int t2 = 0; t2 < d; ++t2)
-                    cmac(th, G[(s1 * d + s2) * d * d + t1 * d + t2],
-                         w.P[((size_t)l * d + t1) * N + (size_t)t2 * chiR + r]);
-            if (orient == 0)
-                w.W[(size_t)col * M + row] = th;
-            else
-                w.W[(size_t)row * N + col] = conj(th);
-        }
-        __syncthreads();
-        factor<T>(D, w, mw, nw, 0, f_t, dec, s_raw, s_sorted, perm, Dsuf, part, sw, cnt);
-        if (!(dec.s0 > 0.0) || !isfinite(dec.total)) {
-            if (tid == 0) {
-                D.status = EA_EINVAL;
-                D.center = center_sh;
-            }
-            return;
-        }
-        const int k = dec.k;
-        const bool right = asc != 0;
-        if (orient == 0) {
-            gather<T>(w.W, M, perm, s_sorted, dec, k, M, 0, right ? -1 : 0, right ? 0 : 1, 1, site[i]);
-            gather<T>(w.V, N, perm, s_sorted, dec, k, N, 1, right ? 1 : 0, right ? 1 : 0, 0, site[i + 1]);
-        } else {
-            gather<T>(w.V, M, perm, s_sorted, dec, k, M, 0, right ? 0 : 1, right ? 0 : 1, 1, site[i]);
-            gather<T>(w.W, N, perm, s_sorted, dec, k, N, 1, right ? 0 : -1, right ? 1 : 0, 0, site[i + 1]);
-        }
-        __syncthreads();
-        if constexpr (sizeof(T) == 4) {
-            if (D.reorth) {
-                if (right)
-                    reorth<T>(w, true, site[i], M, k, site[i + 1], N);
-                else
-                    reorth<T>(w, false, site[i + 1], N, k, site[i], M);
-            }
-        }
-        if (tid == 0) {
-            bond[i + 1] = k;
-            center_sh = right ? i + 1 : i;
-            D.lnP += dec.lnf;
-            if (D.kind == EA_MIXED && dec.kept2 > 0) D.lnS += 0.5 * log(dec.kept2);
-            ea_gate_record &r = D.log[gi];
-            r.gate = D.g;
-            r.site = i;
-            r.chi_l = chiL;
-            r.chi_m = chiM;
-            r.chi_r = chiR;
-            r.k = k;
-            r.k_f = dec.k_f;
-            r.sweeps = dec.sweeps;
-            r.capped = dec.capped;
-            r.f_t = f_t;
-            r.f = dec.f;
-            r.total = dec.total;
-            r.lnP = D.lnP;
-            D.g += 1;
-            if (D.fout) D.fout[j] = dec.f;
-            D.n_capped += dec.capped;
-            D.n_noconv += dec.converged ? 0 : 1;
-            D.n_done = gi + 1;
-        }
+
+        if (tid == 0) D.layers_done = L + 1;
         __syncthreads();
     }
     if (tid == 0) D.center = center_sh;

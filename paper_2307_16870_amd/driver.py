@@ -112,3 +112,30 @@ class EAState:
             rc, _ = self.apply_layer([op.site for op in twos], np.stack([op.mat for op in twos]))
             if rc > 0:
                 self.warnings += 1
+
+
+def run_batched(states, programs, f_min=1.0, strategy=B.EA_GLOBAL, persistent=True):
+    """Advance independent states through their programs together.  With
+    ``persistent`` the leading small-bond layers of all states run in one
+    device-resident launch (``mps_run_layers_batched``); then every remaining
+    layer is one ``mps_apply_layer_batched`` call over the states that still
+    have it.  Programs must hold two-qubit gates only.  Returns the worst
+    status seen."""
+    for st, p in zip(states, programs):
+        st.set_schedule(f_min, max(1, p.n_2q), strategy)
+    done = [0] * len(states)
+    worst = 0
+    if persistent:
+        layers = [[[(op.site, op.mat) for op in layer] for layer in p.layers] for p in programs]
+        rc, _, done = B.mps_run_layers_batched([s.h for s in states], layers)
+        worst = max(worst, rc)
+    depth = max((len(p.layers) for p in programs), default=0)
+    for t in range(min(done, default=0), depth):
+        idx = [b for b, p in enumerate(programs) if done[b] <= t < len(p.layers)]
+        if not idx:
+            continue
+        sites = [[op.site for op in programs[b].layers[t]] for b in idx]
+        ops = [np.stack([op.mat for op in programs[b].layers[t]]) for b in idx]
+        rc, _, _ = B.mps_apply_layer_batched([states[b].h for b in idx], sites, ops)
+        worst = max(worst, rc)
+    return worst

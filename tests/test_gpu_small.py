@@ -119,3 +119,54 @@ def test_small_batched_many_states_one_launch(cols):
         psi_h, F_h, log_h, _ = _run(p, "c128", 0.98, 0)
         assert ks == [r["k"] for r in log_h]
         np.testing.assert_allclose(psi, psi_h, atol=1e-10)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_persistent_launch_then_layer_batches(prec):
+    """The leading small-bond layers of sixteen circuits in one launch, the
+    rest layer by layer, against each circuit run alone on the
+    host-orchestrated path; some circuits outgrow the limit part-way."""
+    _say("case: persistent batched", prec)
+    rng = np.random.default_rng(8)
+    progs = [C.brickwork_program(int(rng.integers(8, 17)), int(rng.integers(4, 15)), 700 + b)
+             for b in range(16)]
+    states = [P.EAState(p.n_sites, "pure", prec) for p in progs]
+    layers = [[[(op.site, op.mat) for op in layer] for layer in p.layers] for p in progs]
+    for st, p in zip(states, progs):
+        st.set_schedule(0.98, p.n_2q)
+    rc, codes, done = P.mps_run_layers_batched([s.h for s in states], layers)
+    assert rc >= 0 and all(c >= 0 for c in codes)
+    _say("layers done on the device:", done, "of", [len(p.layers) for p in progs])
+    assert any(d < len(p.layers) for d, p in zip(done, progs))
+    assert any(d == len(p.layers) for d, p in zip(done, progs))
+    for t in range(max(len(p.layers) for p in progs)):
+        idx = [b for b, p in enumerate(progs) if done[b] <= t < len(p.layers)]
+        if idx:
+            P.mps_apply_layer_batched([states[b].h for b in idx],
+                                      [[op.site for op in progs[b].layers[t]] for b in idx],
+                                      [np.stack([op.mat for op in progs[b].layers[t]]) for b in idx])
+    for st, p in zip(states, progs):
+        psi = st.statevector()
+        F = st.fidelity_estimate()[0]
+        log = st.gate_log()
+        st.close()
+        psi_h, F_h, log_h, _ = _run(p, prec, 0.98, 0)
+        assert len(log) == len(log_h) == p.n_2q
+        if prec == "c128":
+            assert [r["k"] for r in log] == [r["k"] for r in log_h]
+            np.testing.assert_allclose(psi, psi_h, atol=1e-10)
+            assert abs(F - F_h) < 1e-10
+        else:
+            assert np.abs(psi - psi_h).max() < 1e-3
+            assert abs(F - F_h) < 1e-4
+
+
+def test_run_batched_driver():
+    progs = [C.brickwork_program(10, 6, 900 + b) for b in range(4)]
+    states = [P.EAState(p.n_sites, "pure", "c128") for p in progs]
+    P.run_batched(states, progs, 0.99)
+    for st, p in zip(states, progs):
+        psi = st.statevector()
+        st.close()
+        psi_h, _, _, _ = _run(p, "c128", 0.99, 0)
+        np.testing.assert_allclose(psi, psi_h, atol=1e-10)
