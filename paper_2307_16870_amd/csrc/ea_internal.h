@@ -540,8 +540,8 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
             launch_theta_bf16x3(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d,
                                 orient, h->stream);
         else
-            launch_theta<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d,
-                            orient, h->stream);
+            launch_theta_mfma<T>(h->site[i].p, h->site[i + 1].p, G, h->W.p, chiL, chiM, chiR, d,
+                                 orient, h->stream);
     }
     LAUNCHCHK(h);
     TRY(factor_and_decide<T>(h, mw, nw, f_t, 0, forced_k));

@@ -38,6 +38,11 @@ void launch_theta(const void *A, const void *B, const void *G, void *W, int chiL
                   int chiR, int d, int orient, hipStream_t s);
 // FP32 operands split into bf16 hi/lo parts on the bf16 matrix cores
 // (three products per real product, FP32 accumulation); same layout and
+// The contraction on the FP32 / FP64 16x16x4 matrix cores (same layout and
+// epilogue as launch_theta).
+template <typename T>
+void launch_theta_mfma(const void *A, const void *B, const void *G, void *W, int chiL, int chiM,
+                       int chiR, int d, int orient, hipStream_t s);
 // epilogue as launch_theta<float>.
 void launch_theta_bf16x3(const void *A, const void *B, const void *G, void *W, int chiL,
                          int chiM, int chiR, int d, int orient, hipStream_t s);

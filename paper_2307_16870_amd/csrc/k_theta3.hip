@@ -170,3 +170,182 @@ void launch_theta_bf16x3(const void *A, const void *B, const void *G, void *W, i
                                                (const cx<float> *)G, (cx<float> *)W, chiL, chiM,
                                                chiR, orient);
 }
+
+// ---------------------------------------------------------------------------
+// The same contraction in FP32 or FP64 on the matching 16x16x4 matrix cores.
+// A workgroup (4 waves) owns a 64 x 64 tile of C[(l, t1), (t2, r)], i.e.
+// 64/D values of l by 64/D values of r with all D^2 (t1, t2) combinations, so
+// the gate epilogue has every input it needs in LDS.  Each wave computes a
+// 32 x 32 quarter as 2 x 2 MFMA tiles; complex products as four real MFMAs
+// (Re += ar br - ai bi, Im += ar bi + ai br).  K advances in steps of 32;
+// every thread issues all its loads of a step before writing LDS.
+// ---------------------------------------------------------------------------
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaT;
+template <>
+struct MfmaT<float> {
+    typedef f32x4 acc;
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ __forceinline__ acc op(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MfmaT<double> {
+    typedef f64x4 acc;
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    static __device__ __forceinline__ acc op(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int TT = 64;  // C tile edge
+constexpr int TK = 32;  // K step
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_theta_mfma(const cx<T> *__restrict__ A,
+                                                    const cx<T> *__restrict__ B,
+                                                    const cx<T> *__restrict__ G,
+                                                    cx<T> *__restrict__ W, int chiL, int chiM,
+                                                    int chiR, int orient) {
+    using MF = MfmaT<T>;
+    constexpr int TL = TT / D, TR = TT / D;
+    // operand planes: A as [row][k], B transposed as [col][k]; the finished C
+    // tile reuses the space
+    union Smem {
+        struct {
+            T ar[TT][TK + 1], ai[TT][TK + 1];
+            T br[TT][TK + 1], bi[TT][TK + 1];
+        } op;
+        cx<T> c[TT][TT + 1];
+    };
+    __shared__ Smem sm;
+    __shared__ cx<T> Gs[D * D][D * D];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l0 = blockIdx.y * TL, r0 = blockIdx.x * TR;
+    for (int e = tid; e < D * D * D * D; e += 256) Gs[e / (D * D)][e % (D * D)] = G[e];
+    typename MF::acc re[2][2], im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) re[a][b][v] = im[a][b][v] = T(0);
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;  // this wave's quarter
+    const size_t ldb = (size_t)D * chiR;
+    constexpr int PER = TT * TK / 256;
+    for (int k0 = 0; k0 < chiM; k0 += TK) {
+        cx<T> va[PER], vb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            {  // A: row = e / TK, k = e % TK
+                const int row = e / TK, kk = e % TK, gk = k0 + kk, l = l0 + row / D;
+                va[u] = (l < chiL && gk < chiM) ? A[((size_t)l0 * D + row) * chiM + gk]
+                                                : zero_cx<T>();
+            }
+            {  // B: k = e / TT, col = e % TT (col = t2 * TR + rr)
+                const int kk = e / TT, c = e % TT, gk = k0 + kk, t2 = c / TR, r = r0 + c % TR;
+                vb[u] = (r < chiR && gk < chiM) ? B[(size_t)gk * ldb + (size_t)t2 * chiR + r]
+                                                : zero_cx<T>();
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            const int row = e / TK, kk = e % TK;
+            sm.op.ar[row][kk] = va[u].x;
+            sm.op.ai[row][kk] = va[u].y;
+            const int kb = e / TT, c = e % TT;
+            sm.op.br[c][kb] = vb[u].x;
+            sm.op.bi[c][kb] = vb[u].y;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < TK; kk += 4) {
+            const int kq = kk + (lane >> 4), rl = lane & 15;
+            T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                ar[a] = sm.op.ar[wr + 16 * a + rl][kq];
+                ai[a] = sm.op.ai[wr + 16 * a + rl][kq];
+                br[a] = sm.op.br[wc + 16 * a + rl][kq];
+                bi[a] = sm.op.bi[wc + 16 * a + rl][kq];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    re[a][b] = MF::op(ar[a], br[b], re[a][b]);
+                    re[a][b] = MF::op(-ai[a], bi[b], re[a][b]);
+                    im[a][b] = MF::op(ar[a], bi[b], im[a][b]);
+                    im[a][b] = MF::op(ai[a], br[b], im[a][b]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                sm.c[wr + 16 * a + MF::row(lane, v)][wc + 16 * b + (lane & 15)] =
+                    mk<T>(re[a][b][v], im[a][b][v]);
+    __syncthreads();
+    // gate epilogue: one (l, r) per thread and pass; the fastest thread index
+    // follows the contiguous output index
+    for (int e = tid; e < TL * TR; e += 256) {
+        const int ll = orient == 0 ? e % TL : e / TR;
+        const int rr = orient == 0 ? e / TL : e % TR;
+        const int l = l0 + ll, r = r0 + rr;
+        if (l >= chiL || r >= chiR) continue;
+        cx<T> c[D][D];
+#pragma unroll
+        for (int t1 = 0; t1 < D; ++t1)
+#pragma unroll
+            for (int t2 = 0; t2 < D; ++t2) c[t1][t2] = sm.c[ll * D + t1][t2 * TR + rr];
+#pragma unroll
+        for (int s1 = 0; s1 < D; ++s1)
+#pragma unroll
+            for (int s2 = 0; s2 < D; ++s2) {
+                cx<T> th = zero_cx<T>();
+#pragma unroll
+                for (int t1 = 0; t1 < D; ++t1)
+#pragma unroll
+                    for (int t2 = 0; t2 < D; ++t2)
+                        cmac(th, Gs[s1 * D + s2][t1 * D + t2], c[t1][t2]);
+                const size_t row = (size_t)l * D + s1, col = (size_t)s2 * chiR + r;
+                if (orient == 0)
+                    W[col * (size_t)(D * chiL) + row] = th;
+                else
+                    W[row * (size_t)(D * chiR) + col] = conj(th);
+            }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_theta_mfma(const void *A, const void *B, const void *G, void *W, int chiL, int chiM,
+                       int chiR, int d, int orient, hipStream_t s) {
+    if (d == 2) {
+        dim3 grid((chiR + TT / 2 - 1) / (TT / 2), (chiL + TT / 2 - 1) / (TT / 2));
+        k_theta_mfma<T, 2><<<grid, 256, 0, s>>>((const cx<T> *)A, (const cx<T> *)B,
+                                                (const cx<T> *)G, (cx<T> *)W, chiL, chiM, chiR,
+                                                orient);
+    } else {
+        dim3 grid((chiR + TT / 4 - 1) / (TT / 4), (chiL + TT / 4 - 1) / (TT / 4));
+        k_theta_mfma<T, 4><<<grid, 256, 0, s>>>((const cx<T> *)A, (const cx<T> *)B,
+                                                (const cx<T> *)G, (cx<T> *)W, chiL, chiM, chiR,
+                                                orient);
+    }
+}
+template void launch_theta_mfma<float>(const void *, const void *, const void *, void *, int, int,
+                                       int, int, int, hipStream_t);
+template void launch_theta_mfma<double>(const void *, const void *, const void *, void *, int,
+                                        int, int, int, int, hipStream_t);
