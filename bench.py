@@ -285,6 +285,49 @@ def bench_hea32(args, torch, C, P):
     print(json.dumps(out), flush=True)
 
 
+def bench_contraction(args, torch, C, P):
+    """The two-site contraction with the gate (one launch per update) alone, at
+    chi = 256, 512 and 1024 (Theta up to 2048 x 2048, K = chi), in every
+    precision: device time per launch from HIP events and the fraction of the
+    matrix-core peak of its arithmetic type.  The SVD after it is cut to one
+    sweep (its time is not counted)."""
+    import numpy as np
+    peak = {"c64": PEAKS["f32_mfma_TF"], "c128": PEAKS["f64_mfma_TF"],
+            "bf16x3": PEAKS["f32_mfma_TF"]}
+    rows = []
+    G = C.haar_unitary(np.random.default_rng(1))
+    for prec in ("c64", "c128", "bf16x3"):
+        for chi in (256, 512, 1024):
+            tens = C.random_mps_tensors([1, chi, chi, chi, 1], 2, seed=chi)
+            st = P.EAState(4, "pure", prec)
+            st.set_option(P.EA_OPT_MAX_SWEEPS, 1)
+            st.load(tens, 1)
+            st.apply_2q(1, G, 0.99)  # loads the code objects
+            st.profile(True)
+            for _ in range(max(1, args.steps)):
+                st.load(tens, 1)
+                st.apply_2q(1, G, 0.99)
+            f = st.profile_read(P.EA_K_THETA)
+            st.close()
+            tf = f["flops"] / f["ms"] / 1e9
+            rows.append({"prec": prec, "chi": chi, "us_per_launch": 1000 * f["ms"] / f["launches"],
+                         "algorithmic_TFLOPs": tf, "frac_of_mfma_peak": tf / peak[prec]})
+            log(f"{prec} chi={chi}: {tf:.1f} TFLOP/s")
+    big = [r for r in rows if r["chi"] == 1024 and r["prec"] == args.prec][0]
+    out = {
+        "metric": "two-site contraction + gate, TFLOP/s at chi = 1024 (Theta 2048 x 2048)",
+        "value": big["algorithmic_TFLOPs"], "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": max(1, args.steps), "warmup": 1, "ms_per_step": big["us_per_launch"] / 1000,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "c128" else "f32", "data": "synthetic",
+        "config": {"workload": "theta-contraction-chi256-512-1024", "prec": args.prec},
+        "roofline": {"bound": "mfma", "achieved": big["algorithmic_TFLOPs"], "peak": peak[args.prec],
+                     "unit": "TFLOP/s", "frac": big["frac_of_mfma_peak"], "traffic": None},
+        "sizes": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,10 +341,11 @@ def main():
     ap.add_argument("--cpu-layers", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--workload", default="brickwork50",
-                    choices=["brickwork50", "batched", "mpo40", "hea32"],
+                    choices=["brickwork50", "batched", "mpo40", "hea32", "contraction"],
                     help="brickwork50: the 50-qubit depth-20 circuit (default); batched: "
                          "independent circuits of the batched workload advanced together; "
-                         "mpo40: the noisy 40-qubit MPO circuit; hea32: adjoint gradients")
+                         "mpo40: the noisy 40-qubit MPO circuit; hea32: adjoint gradients; "
+                         "contraction: the two-site contraction alone at chi <= 1024")
     ap.add_argument("--circuits", type=int, default=16, help="batched: number of circuits")
     ap.add_argument("--max-depth", type=int, default=12, help="batched: depth cap per circuit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -331,6 +375,8 @@ def main():
         return bench_mpo40(args, torch, C, P)
     if args.workload == "hea32":
         return bench_hea32(args, torch, C, P)
+    if args.workload == "contraction":
+        return bench_contraction(args, torch, C, P)
     stream = torch.cuda.current_stream()
     prog, cfg = C.config_program(2, depth=args.depth)
     f_min, chi_max = cfg["f_min"], cfg["chi_max"]
