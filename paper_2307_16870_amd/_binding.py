@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libeamps.so")
+# EA_MPS_LIB may name another build of the same library (for example one
+# built with different tuning constants); default: the in-tree build.
+LIB_PATH = os.environ.get("EA_MPS_LIB") or os.path.join(_HERE, "_lib", "libeamps.so")
 
 EA_PURE, EA_MIXED = 0, 1
 EA_C128, EA_C64, EA_C64_BF16X3 = 0, 1, 2

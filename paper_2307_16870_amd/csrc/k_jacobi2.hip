@@ -434,7 +434,7 @@ static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, 
                        double tol, int inner_max, int inter, void *partial, void *J,
                        int *rotflag, int *rot_counter, int rot_threads, hipStream_t s) {
     const int npairs = nb / 2;
-    const int nchG = chunks_for(m, npairs, 512);
+    const int nchG = chunks_for(m, npairs, 256);
     const int rpcG = rows_per_chunk(m, nchG);
     const int nchG_eff = (m + rpcG - 1) / rpcG;
     if (part == 0) {
@@ -459,7 +459,7 @@ static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, 
         else EA_JEIG(1024);
 #undef EA_JEIG
     } else {
-        const int nchW = chunks_for(m, npairs, 512), rpcW = rows_per_chunk(m, nchW);
+        const int nchW = chunks_for(m, npairs, 256), rpcW = rows_per_chunk(m, nchW);
         const int nchV = chunks_for(n, npairs, 512), rpcV = rows_per_chunk(n, nchV);
         const int nW = (m + rpcW - 1) / rpcW, nV = (n + rpcV - 1) / rpcV;
         k_japply<T, NC><<<dim3(npairs, nW + nV), 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb,
@@ -474,7 +474,7 @@ size_t jacobi_round3_partial_elems(int m, int n, int w) {
     int nb = (n + w - 1) / w;
     nb += nb & 1;
     const int npairs = nb / 2;
-    const int nchG = chunks_for(m, npairs, 512);
+    const int nchG = chunks_for(m, npairs, 256);
     const int rpcG = rows_per_chunk(m, nchG);
     const int nchG_eff = (m + rpcG - 1) / rpcG;
     return (size_t)npairs * nchG_eff * nc * nc;
