@@ -97,12 +97,17 @@ enum ea_option {
                                 rounds rotate only pairs across the two blocks (every pair
                                 once per sweep); 0 rotates all pairs of the block pair in
                                 every round */
-    EA_OPT_SMALL_LAYERS = 10 /* c = 64 (default) or 128: a layer whose every bond is at
+    EA_OPT_SMALL_LAYERS = 10, /* c = 64 (default) or 128: a layer whose every bond is at
                                 most c / d runs as one device-resident launch (one
                                 workgroup per state walks the layer, sizes read on the
                                 device, no host synchronisation between its gates;
                                 mps_apply_layer and mps_apply_layer_batched, where all
                                 such states share one launch); 0: host-orchestrated */
+    EA_OPT_JACOBI_SKIP = 11  /* three-kernel Jacobi: 1 (default) skips a column block pair
+                                whose two blocks are unchanged since the pair was last
+                                examined (it would find the same Gram matrix and no
+                                rotation, so results are bit-identical); 0 examines every
+                                pair in every sweep */
 };
 
 /* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */

@@ -101,7 +101,7 @@ void mps_free(ea_mps *h) {
     h->adj = nullptr;
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     for (auto &b : h->site) free_buf(b);
-    DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
+    DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->jstamp, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
                       &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_loff, &h->sm_gsite,
                       &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs};
@@ -157,6 +157,10 @@ int mps_set_option(ea_mps *h, int option, double value) {
     case EA_OPT_JACOBI_ORDER:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi order must be 0 or 1");
         h->jorder = (int)value;
+        return EA_OK;
+    case EA_OPT_JACOBI_SKIP:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi skip must be 0 or 1");
+        h->jskip = value != 0;
         return EA_OK;
     case EA_OPT_ROT_THREADS:
         if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512 &&

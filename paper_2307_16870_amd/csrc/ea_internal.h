@@ -54,7 +54,8 @@ struct ea_mps {
     long n_total = 1;
     int strategy = EA_GLOBAL;
     // workspace
-    ea::DevBuf jpart, jmat, jflag;
+    ea::DevBuf jpart, jmat, jflag, jstamp;
+    bool jskip = true;  // skip block pairs unchanged since they were last examined
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
     int inner_round = 1, jkernel = 0, rot_threads = 0;  // 0: 16 per column of a block pair
@@ -276,44 +277,52 @@ int svd_core(ea_mps *h, int m, int n) {
         TRY(ensure(h, h->jpart, h->csz * jacobi_round3_partial_elems(m, n, w)));
         TRY(ensure(h, h->jmat, h->csz * jacobi_round3_j_elems(n, w)));
         TRY(ensure(h, h->jflag, sizeof(int) * (nb / 2 + 1)));
+        if (h->jskip) {
+            TRY(ensure(h, h->jstamp, sizeof(int) * jacobi_stamp_ints(nb)));
+            launch_fill_int((int *)h->jstamp.p, (int)jacobi_stamp_ints(nb), 0, h->stream);
+        }
     }
+    int *stamp = three && h->jskip ? (int *)h->jstamp.p : nullptr;
     int sweeps = 0, conv = 0;
     for (int sw = 0; sw < h->max_sweeps; ++sw) {
-        launch_fill_int(counter, 1, 0, h->stream);
+        launch_fill_int(counter, 3, 0, h->stream);
         for (int rnd = 0; rnd < nb - 1; ++rnd) {
             // pairs inside a block are rotated in the sweep's first round only
             const int inter = (h->jorder == 1 && rnd > 0) ? 1 : 0;
-            // algorithmic work of one round: every column block pair forms its
-            // Hermitian Gram matrix (4 m nc^2 flops) and rotates its nc columns of W
-            // and V (8 (m + n) nc^2 flops)
-            double fl2 = 0.0;
-            for (int p = 0; p < nb / 2; ++p) {
-                const int a = p == 0 ? 0 : (p - 1 + rnd) % (nb - 1) + 1;
-                const int bq = nb - 1 - p;
-                const int b = bq == 0 ? 0 : (bq - 1 + rnd) % (nb - 1) + 1;
-                const int nc = std::max(0, std::min(w, n - a * w)) + std::max(0, std::min(w, n - b * w));
-                fl2 += (double)nc * nc;
-            }
             if (three) {
+                // algorithmic work is counted per sweep from the pairs examined
+                // and rotated (below)
                 {
-                    ProfScope ps(h, EA_K_JGRAM, 4.0 * m * fl2, c * m * (double)n);
+                    ProfScope ps(h, EA_K_JGRAM, 0.0, c * m * (double)n);
                     launch_jacobi_part<T>(0, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          rot_threads, h->stream);
+                                          stamp, rot_threads, h->stream);
                 }
                 {
                     ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * 64.0 * 64.0);
                     launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          rot_threads, h->stream);
+                                          stamp, rot_threads, h->stream);
                 }
                 {
-                    ProfScope ps(h, EA_K_JAPPLY, 8.0 * (m + n) * fl2, 2.0 * c * (m + n) * (double)n);
+                    ProfScope ps(h, EA_K_JAPPLY, 0.0, 2.0 * c * (m + n) * (double)n);
                     launch_jacobi_part<T>(2, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          rot_threads, h->stream);
+                                          stamp, rot_threads, h->stream);
                 }
             } else {
+                // algorithmic work of one round: every column block pair forms its
+                // Hermitian Gram matrix (4 m nc^2 flops) and rotates its nc columns
+                // of W and V (8 (m + n) nc^2 flops)
+                double fl2 = 0.0;
+                for (int p = 0; p < nb / 2; ++p) {
+                    const int a = p == 0 ? 0 : (p - 1 + rnd) % (nb - 1) + 1;
+                    const int bq = nb - 1 - p;
+                    const int b = bq == 0 ? 0 : (bq - 1 + rnd) % (nb - 1) + 1;
+                    const int nc = std::max(0, std::min(w, n - a * w)) +
+                                   std::max(0, std::min(w, n - b * w));
+                    fl2 += (double)nc * nc;
+                }
                 ProfScope ps(h, EA_K_JFUSED, (4.0 * m + 8.0 * (m + n)) * fl2,
                              2.0 * c * (m + n) * (double)n);
                 launch_jacobi_round<T>(h->W.p, m, h->V.p, n, w, nb, rnd, tol, 6, ncmax, counter,
@@ -321,13 +330,19 @@ int svd_core(ea_mps *h, int m, int n) {
             }
         }
         LAUNCHCHK(h);
-        HIPCHK(h, hipMemcpyAsync(h->int_host, counter, sizeof(int), hipMemcpyDeviceToHost,
+        HIPCHK(h, hipMemcpyAsync(h->int_host, counter, 3 * sizeof(int), hipMemcpyDeviceToHost,
                                  h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
         ++sweeps;
-        // algorithmic work of the rotations of this sweep: each rotation updates
-        // two rows of the Hermitian Gram matrix and two columns of J (48 nc flops)
-        if (h->prof_on && three) h->prof_flops[EA_K_JROT] += 48.0 * 2 * w * (double)h->int_host[0];
+        // algorithmic work of this sweep: each rotation updates two rows of the
+        // Hermitian Gram matrix and two columns of J (48 nc flops); each pair
+        // examined forms its Gram matrix (4 m nc^2 flops); each pair rotated
+        // multiplies its nc columns of W and V by J (8 (m + n) nc^2 flops)
+        if (h->prof_on && three) {
+            h->prof_flops[EA_K_JROT] += 48.0 * 2 * w * (double)h->int_host[0];
+            h->prof_flops[EA_K_JGRAM] += 4.0 * m * (double)h->int_host[1];
+            h->prof_flops[EA_K_JAPPLY] += 8.0 * (m + n) * (double)h->int_host[2];
+        }
         if (h->int_host[0] == 0) {
             conv = 1;
             break;

@@ -54,6 +54,20 @@ __device__ __forceinline__ int pair_columns(int pair, int rnd, int nb, int w, in
     return na + nbb;
 }
 
+// Change stamps of a factorisation (zero at its start): ver[b] (b < nb) counts
+// the rounds that rotated column block b; seen[2 (rnd nb/2 + pair)] holds
+// ver + 1 of the pair's two blocks when round rnd last examined the pair (0:
+// never).  The pairing of a round is the same in every sweep, so a pair whose
+// blocks are unchanged since that examination would form the same Gram
+// matrix from bit-identical columns and again find no rotation (had it
+// rotated, both stamps would have moved since): such a pair is skipped.
+__device__ __forceinline__ bool pair_unchanged(const int *stamp, int nb, int rnd, int pair) {
+    if (!stamp) return false;
+    const int a = rr_player(pair, rnd, nb), b = rr_player(nb - 1 - pair, rnd, nb);
+    const int *seen = stamp + nb + 2 * (rnd * (nb / 2) + pair);
+    return seen[0] == stamp[a] + 1 && seen[1] == stamp[b] + 1;
+}
+
 constexpr int JRS = 64;  // rows staged in LDS per step
 
 // Load rows [r0, r0+JRS) of the owned columns into split real/imag LDS planes,
@@ -82,7 +96,8 @@ __device__ __forceinline__ void stage_rows(const cx<T> *__restrict__ X, int M, c
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int m, int n, int w,
                                                int nb, int rnd, int rpc,
-                                               cx<T> *__restrict__ partial) {
+                                               cx<T> *__restrict__ partial,
+                                               const int *__restrict__ stamp) {
     using MF = Mfma<T>;
     constexpr int NT = NC / 16;
     constexpr int NU = NT * (NT + 1) / 2;  // upper-triangular 16x16 tiles
@@ -91,6 +106,7 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
     __shared__ int cols[NC];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int pair = blockIdx.x, chunk = blockIdx.y, nchunks = gridDim.y;
+    if (pair_unchanged(stamp, nb, rnd, pair)) return;
     const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, 256);
     const int r_begin = chunk * rpc, r_end = min(m, r_begin + rpc);
     int ti_[UPW], tj_[UPW];
@@ -150,7 +166,8 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                                               int inner_max,
                                               cx<T> *__restrict__ Jout,
                                               int *__restrict__ rotflag,
-                                              int *__restrict__ rot_counter) {
+                                              int *__restrict__ rot_counter,
+                                              int *__restrict__ stamp) {
     constexpr int NP = NC / 2;
     __shared__ cx<T> G[NC][NC + 1];
     __shared__ cx<T> J[NC][NC + 1];
@@ -160,6 +177,10 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     __shared__ int cols[NC];
     __shared__ int nrot_sh[2];
     const int tid = threadIdx.x, pair = blockIdx.x;
+    if (pair_unchanged(stamp, nb, rnd, pair)) {
+        if (tid == 0) rotflag[pair] = 0;
+        return;
+    }
     const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, NTH);
     // sum the partial Gram tiles (upper triangle) in a fixed order
     const cx<T> *src = partial + (size_t)pair * nchunks * NC * NC;
@@ -334,7 +355,21 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     }
     if (tid == 0) {
         rotflag[pair] = first > 0 ? 1 : 0;
-        if (first > 0) atomicAdd(rot_counter, first);
+        atomicAdd(rot_counter + 1, nc * nc);
+        if (first > 0) {
+            atomicAdd(rot_counter, first);
+            atomicAdd(rot_counter + 2, nc * nc);
+        }
+        if (stamp) {
+            const int a = rr_player(pair, rnd, nb), b = rr_player(nb - 1 - pair, rnd, nb);
+            int *seen = stamp + nb + 2 * (rnd * (nb / 2) + pair);
+            seen[0] = stamp[a] + 1;
+            seen[1] = stamp[b] + 1;
+            if (first > 0) {  // blocks a and b belong to this pair alone in this round
+                stamp[a] += 1;
+                stamp[b] += 1;
+            }
+        }
     }
 }
 
@@ -432,25 +467,28 @@ static int rows_per_chunk(int rows, int nch) {
 template <typename T, int NC>
 static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
                        double tol, int inner_max, int inter, void *partial, void *J,
-                       int *rotflag, int *rot_counter, int rot_threads, hipStream_t s) {
+                       int *rotflag, int *rot_counter, int *stamp, int rot_threads,
+                       hipStream_t s) {
     const int npairs = nb / 2;
     const int nchG = chunks_for(m, npairs, 256);
     const int rpcG = rows_per_chunk(m, nchG);
     const int nchG_eff = (m + rpcG - 1) / rpcG;
     if (part == 0) {
         k_jgram<T, NC><<<dim3(npairs, nchG_eff), 256, 0, s>>>((const cx<T> *)W, m, n, w, nb, rnd,
-                                                            rpcG, (cx<T> *)partial);
+                                                            rpcG, (cx<T> *)partial, stamp);
     } else if (part == 1) {
 #define EA_JEIG(NTH)                                                                          \
     do {                                                                                      \
         if (inter)                                                                            \
             k_jeig<T, NC, NTH, 1><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, \
                                                          w, nb, rnd, (T)tol, inner_max,       \
-                                                         (cx<T> *)J, rotflag, rot_counter);   \
+                                                         (cx<T> *)J, rotflag, rot_counter,    \
+                                                         stamp);                              \
         else                                                                                  \
             k_jeig<T, NC, NTH, 0><<<npairs, NTH, 0, s>>>((const cx<T> *)partial, nchG_eff, n, \
                                                          w, nb, rnd, (T)tol, inner_max,       \
-                                                         (cx<T> *)J, rotflag, rot_counter);   \
+                                                         (cx<T> *)J, rotflag, rot_counter,    \
+                                                         stamp);                              \
     } while (0)
         if (rot_threads <= 64) EA_JEIG(64);
         else if (rot_threads <= 128) EA_JEIG(128);
@@ -489,16 +527,19 @@ size_t jacobi_round3_j_elems(int n, int w) {
 template <typename T>
 void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
                         double tol, int inner_max, int inter, void *partial, void *J,
-                        int *rotflag, int *rot_counter, int rot_threads, hipStream_t s) {
+                        int *rotflag, int *rot_counter, int *stamp, int rot_threads,
+                        hipStream_t s) {
     if (2 * w <= 32)
         round_part<T, 32>(part, W, m, V, n, w, nb, rnd, tol, inner_max, inter, partial, J,
-                          rotflag, rot_counter, rot_threads, s);
+                          rotflag, rot_counter, stamp, rot_threads, s);
     else
         round_part<T, 64>(part, W, m, V, n, w, nb, rnd, tol, inner_max, inter, partial, J,
-                          rotflag, rot_counter, rot_threads, s);
+                          rotflag, rot_counter, stamp, rot_threads, s);
 }
 
 template void launch_jacobi_part<float>(int, void *, int, void *, int, int, int, int, double, int,
-                                        int, void *, void *, int *, int *, int, hipStream_t);
+                                        int, void *, void *, int *, int *, int *, int,
+                                        hipStream_t);
 template void launch_jacobi_part<double>(int, void *, int, void *, int, int, int, int, double,
-                                         int, int, void *, void *, int *, int *, int, hipStream_t);
+                                         int, int, void *, void *, int *, int *, int *, int,
+                                         hipStream_t);
