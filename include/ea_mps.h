@@ -274,16 +274,19 @@ enum ea_kfamily {
     EA_K_COUNT = 12
 };
 
-/* enable = 1: start timing every kernel launch of this handle with a pair of
- * HIP events on its stream (counters reset); 0: stop.  Adds a small
- * per-launch overhead. */
-int mps_profile(ea_mps *h, int enable);
+/* every >= 1: reset the counters and start counting every kernel launch of
+ * this handle with its algorithmic flops and bytes, and timing one launch in
+ * `every` of each family (the 1st, (every+1)th, ...) with a pair of HIP events
+ * on its stream; every = 1 times all launches (each event pair adds host and
+ * device overhead to the run).  0: stop.  EA_EINVAL if every < 0. */
+int mps_profile(ea_mps *h, int every);
 
-/* Accumulated device time (ms), number of launches, and the algorithmic
- * floating-point operations and bytes of those launches for one family.
+/* For one family: the device time (ms) of the timed launches and their
+ * number, the number of all launches and their algorithmic floating-point
+ * operations and bytes.  The average launch time is ms_timed / timed.
  * Synchronises the handle's stream.  Any output pointer may be NULL. */
-int mps_profile_read(ea_mps *h, int family, double *ms_total, long *launches,
-                     double *flops, double *bytes);
+int mps_profile_read(ea_mps *h, int family, double *ms_timed, long *launches,
+                     double *flops, double *bytes, long *timed);
 
 /* ---- Differentiation (adjoint of the update with kept ranks frozen) ---- */
 

@@ -88,7 +88,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_get_site": (I, [P, I, dp, S, ip]),
         "mps_reset_product": (I, [P, dp]),
         "mps_profile": (I, [P, I]),
-        "mps_profile_read": (I, [P, I, dp, ct.POINTER(ct.c_long), dp, dp]),
+        "mps_profile_read": (I, [P, I, dp, ct.POINTER(ct.c_long), dp, dp, ct.POINTER(ct.c_long)]),
         "mps_apply_layer_batched": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(dp),
                                         ct.POINTER(dp), ct.POINTER(dp), ip]),
         "mps_run_layers_batched": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(ip),
@@ -249,16 +249,21 @@ def mps_reset_product(h, local=None):
     return _chk(_lib.mps_reset_product(h, _dp(loc) if loc is not None else None))
 
 
-def mps_profile(h, enable):
-    return _chk(_lib.mps_profile(h, int(bool(enable))))
+def mps_profile(h, every):
+    """every: 0 stops; k >= 1 times one launch in k per family (True = 1)."""
+    return _chk(_lib.mps_profile(h, int(every)))
 
 
 def mps_profile_read(h, family):
-    """Returns dict(ms, launches, flops, bytes) for one kernel family."""
-    ms, n, fl, by = ct.c_double(), ct.c_long(), ct.c_double(), ct.c_double()
+    """One kernel family: dict(ms, ms_timed, timed, avg_ms, launches, flops,
+    bytes); ms = avg_ms * launches estimates the device time of all launches
+    from the timed ones."""
+    ms, n, fl, by, nt = ct.c_double(), ct.c_long(), ct.c_double(), ct.c_double(), ct.c_long()
     _chk(_lib.mps_profile_read(h, int(family), ct.byref(ms), ct.byref(n), ct.byref(fl),
-                               ct.byref(by)))
-    return {"ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value}
+                               ct.byref(by), ct.byref(nt)))
+    avg = ms.value / nt.value if nt.value else 0.0
+    return {"ms": avg * n.value, "ms_timed": ms.value, "timed": nt.value, "avg_ms": avg,
+            "launches": n.value, "flops": fl.value, "bytes": by.value}
 
 
 def mps_apply_layer_batched(handles, sites_list, ops_list, budgets_list=None):

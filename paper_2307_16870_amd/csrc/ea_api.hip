@@ -687,27 +687,30 @@ int mps_reset_product(ea_mps *h, const double *local) {
     return EA_OK;
 }
 
-int mps_profile(ea_mps *h, int enable) {
+int mps_profile(ea_mps *h, int every) {
     TRY(check(h));
+    if (every < 0) return set_err(EA_EINVAL, "profile period < 0");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     prof_harvest(h);
-    if (enable) {
+    if (every) {
         for (int f = 0; f < EA_K_COUNT; ++f) {
             h->prof_ms[f] = h->prof_flops[f] = h->prof_bytes[f] = 0.0;
-            h->prof_cnt[f] = 0;
+            h->prof_cnt[f] = h->prof_timed[f] = 0;
         }
+        h->prof_every = every;
     }
-    h->prof_on = enable != 0;
+    h->prof_on = every != 0;
     return EA_OK;
 }
 
-int mps_profile_read(ea_mps *h, int family, double *ms_total, long *launches, double *flops,
-                     double *bytes) {
+int mps_profile_read(ea_mps *h, int family, double *ms_timed, long *launches, double *flops,
+                     double *bytes, long *timed) {
     TRY(check(h));
     if (family < 0 || family >= EA_K_COUNT) return set_err(EA_EINVAL, "bad kernel family");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     prof_harvest(h);
-    if (ms_total) *ms_total = h->prof_ms[family];
+    if (ms_timed) *ms_timed = h->prof_ms[family];
+    if (timed) *timed = h->prof_timed[family];
     if (launches) *launches = h->prof_cnt[family];
     if (flops) *flops = h->prof_flops[family];
     if (bytes) *bytes = h->prof_bytes[family];

@@ -85,13 +85,13 @@ struct ea_mps {
     struct ProfRec {
         hipEvent_t a, b;
         int fam;
-        double flops, bytes;
     };
     bool prof_on = false;
+    int prof_every = 1;  // one launch in prof_every of each family is timed
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     double prof_ms[EA_K_COUNT] = {0}, prof_flops[EA_K_COUNT] = {0}, prof_bytes[EA_K_COUNT] = {0};
-    long prof_cnt[EA_K_COUNT] = {0};
+    long prof_cnt[EA_K_COUNT] = {0}, prof_timed[EA_K_COUNT] = {0};
 };
 
 
@@ -125,21 +125,26 @@ inline hipEvent_t ev_get(ea_mps *h) {
     return e;
 }
 
-// Times the launches enqueued during its lifetime with an event pair.
+// Counts the launches enqueued during its lifetime with their algorithmic
+// flops and bytes, and times every prof_every-th of them per family with an
+// event pair.
 struct ProfScope {
     ea_mps *h;
     hipEvent_t a = nullptr;
     int fam;
-    double fl, by;
-    ProfScope(ea_mps *h_, int fam_, double fl_, double by_) : h(h_), fam(fam_), fl(fl_), by(by_) {
-        if (h->prof_on && (a = ev_get(h)) != nullptr) (void)hipEventRecord(a, h->stream);
+    ProfScope(ea_mps *h_, int fam_, double fl, double by) : h(h_), fam(fam_) {
+        if (!h->prof_on) return;
+        const long k = h->prof_cnt[fam]++;
+        h->prof_flops[fam] += fl;
+        h->prof_bytes[fam] += by;
+        if (k % h->prof_every == 0 && (a = ev_get(h)) != nullptr) (void)hipEventRecord(a, h->stream);
     }
     ~ProfScope() {
         if (!a) return;
         hipEvent_t b = ev_get(h);
         if (!b) return;
         (void)hipEventRecord(b, h->stream);
-        h->prof_pending.push_back({a, b, fam, fl, by});
+        h->prof_pending.push_back({a, b, fam});
     }
 };
 
@@ -149,9 +154,7 @@ inline void prof_harvest(ea_mps *h) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             h->prof_ms[r.fam] += ms;
-            h->prof_cnt[r.fam] += 1;
-            h->prof_flops[r.fam] += r.flops;
-            h->prof_bytes[r.fam] += r.bytes;
+            h->prof_timed[r.fam] += 1;
         }
         h->prof_pool.push_back(r.a);
         h->prof_pool.push_back(r.b);
@@ -299,7 +302,10 @@ int svd_core(ea_mps *h, int m, int n) {
                                           stamp, rot_threads, h->stream);
                 }
                 {
-                    ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * 64.0 * 64.0);
+                    // per block pair: the Hermitian Gram matrix (upper triangle) in,
+                    // the accumulated rotation J out
+                    const double ncd = 2 * w <= 32 ? 32.0 : 64.0;
+                    ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * (ncd * (ncd + 1) / 2 + ncd * ncd));
                     launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
                                           stamp, rot_threads, h->stream);
