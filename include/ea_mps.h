@@ -110,6 +110,35 @@ enum ea_option {
                                 pair in every sweep */
 };
 
+/* ---- Launch-shape tuning (written by the package's autotuner) ---- */
+
+/* One entry of the process-wide tuning table of the three-kernel Jacobi. */
+typedef struct ea_tune_entry {
+    int32_t f64;         /* 0: FP32 working data (EA_C64, EA_C64_BF16X3); 1: EA_C128 */
+    int32_t n_max;       /* covers factorisations of n <= n_max columns not covered
+                            by an entry of the same f64 with a smaller n_max */
+    int32_t block;       /* column-block width: 16 or 32 */
+    int32_t rot_threads; /* threads of the rotation kernel: 64, 128, 256, 512, 1024 */
+    int32_t chunk_wgs;   /* workgroups targeted by the Gram and apply launches, 64..4096 */
+} ea_tune_entry;
+
+/* Replace the process-wide tuning table (copied; n_entries = 0 clears it).
+ * A factorisation of n > 64 columns on the three-kernel Jacobi takes the
+ * entry of its precision with the smallest n_max >= n: its row-chunk target
+ * always, its block width when the handle's EA_OPT_BLOCK is 0, and its
+ * rotation threads when EA_OPT_BLOCK and EA_OPT_ROT_THREADS are both 0 (a set
+ * option wins).  Without an entry: block 32, 1024 rotation threads (512 at
+ * block 16), 256 workgroups.  Results depend on
+ * the block width only through rounding.  EA_EINVAL, table unchanged, on a
+ * malformed entry or two entries with the same (f64, n_max).  Host only (no
+ * device call); safe to call from any thread, a factorisation already
+ * running keeps the shape it chose. */
+int mps_set_tuning(int n_entries, const ea_tune_entry *entries);
+
+/* Copies up to `capacity` entries of the table, sorted by (f64, n_max), into
+ * out; returns the number of entries (or EA_EINVAL). */
+int mps_get_tuning(int capacity, ea_tune_entry *out);
+
 /* One record per two-site update (Sec. VI bookkeeping; Figs. 1-4 plot these). */
 typedef struct ea_gate_record {
     int64_t gate;    /* 0-based index among two-qubit updates */

@@ -32,6 +32,7 @@ SYMBOLS = [
     "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
     "mps_apply_layer_batched", "mps_run_layers_batched", "mps_energy_grad", "ea_last_error",
+    "mps_set_tuning", "mps_get_tuning",
 ]
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
@@ -54,6 +55,12 @@ class DOp(ct.Structure):
     """One op of a differentiable circuit (ea_dop)."""
     _fields_ = [("kind", ct.c_int32), ("site", ct.c_int32), ("param", ct.c_int32),
                 ("layer_end", ct.c_int32), ("mat", ct.c_double * 32)]
+
+
+class TuneEntry(ct.Structure):
+    """One entry of the process-wide Jacobi launch-shape table (ea_tune_entry)."""
+    _fields_ = [("f64", ct.c_int32), ("n_max", ct.c_int32), ("block", ct.c_int32),
+                ("rot_threads", ct.c_int32), ("chunk_wgs", ct.c_int32)]
 
 
 class GateRecord(ct.Structure):
@@ -95,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
                                        ct.POINTER(dp), ip, ip]),
         "mps_energy_grad": (I, [P, I, ct.POINTER(DOp), dp, I, I, ip, ip, dp, dp, D, D, dp, dp, dp]),
         "ea_last_error": (ct.c_char_p, []),
+        "mps_set_tuning": (I, [I, ct.POINTER(TuneEntry)]),
+        "mps_get_tuning": (I, [I, ct.POINTER(TuneEntry)]),
     }
     for name, (res, args) in sig.items():
         try:
@@ -107,6 +116,13 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
     return lib
 
 
+# PyTorch bundles its own HIP runtime.  Loaded after this library, it becomes a
+# second runtime in the process, and whichever initialises second sees no
+# device; importing torch first makes this library bind to torch's runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = load_library()
 
 
@@ -378,3 +394,32 @@ def mps_energy_grad(h, dops, params, terms, f_min=1.0, eta_rel=0.0):
                               _ip(widths), _dp(ops), _dp(coefs), float(f_min), float(eta_rel),
                               ct.byref(E), _dp(grad), ct.byref(lnP)))
     return E.value, grad, lnP.value
+
+
+_TUNE_KEYS = ("f64", "n_max", "block", "rot_threads", "chunk_wgs")
+
+
+def mps_set_tuning(entries):
+    """Replace the process-wide Jacobi launch-shape table; entries: dicts with
+    keys f64, n_max, block, rot_threads, chunk_wgs ([] clears it)."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        for k in _TUNE_KEYS:
+            setattr(arr[i], k, int(e[k]))
+    return _chk(_lib.mps_set_tuning(len(entries), arr))
+
+
+def mps_get_tuning():
+    """The current table as a list of dicts sorted by (f64, n_max)."""
+    n = _chk(_lib.mps_get_tuning(0, None))
+    arr = (TuneEntry * max(1, n))()
+    _chk(_lib.mps_get_tuning(n, arr))
+    return [{k: getattr(arr[i], k) for k in _TUNE_KEYS} for i in range(n)]
+
+
+def load_tuning(path):
+    """Install the table stored by the autotuner (JSON with an "entries" list)."""
+    import json
+    with open(path) as fh:
+        return mps_set_tuning(json.load(fh)["entries"])
+

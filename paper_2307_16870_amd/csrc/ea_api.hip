@@ -3,8 +3,26 @@
 // the orchestration of the kernels of one two-site update.
 #include "ea_internal.h"
 
+#include <mutex>
+
 namespace ea {
 thread_local std::string g_err;
+
+// Process-wide tuning table (mps_set_tuning), entries sorted by (f64, n_max).
+static std::mutex g_tune_mu;
+static std::vector<ea_tune_entry> g_tune;
+
+bool tune_lookup(bool f64, int n, int *block, int *rot_threads, int *wgs) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &e : g_tune)
+        if ((e.f64 != 0) == f64 && n <= e.n_max) {
+            *block = e.block;
+            *rot_threads = e.rot_threads;
+            *wgs = e.chunk_wgs;
+            return true;
+        }
+    return false;
+}
 }  // namespace ea
 
 using namespace ea;
@@ -15,6 +33,37 @@ using namespace ea;
 extern "C" {
 
 const char *ea_last_error(void) { return g_err.c_str(); }
+
+int mps_set_tuning(int n_entries, const ea_tune_entry *entries) {
+    if (n_entries < 0) return set_err(EA_EINVAL, "n_entries < 0");
+    if (n_entries > 0 && !entries) return set_err(EA_EINVAL, "entries is NULL");
+    std::vector<ea_tune_entry> t(entries, entries + n_entries);
+    for (int i = 0; i < n_entries; ++i) {
+        const ea_tune_entry &e = t[i];
+        const int rt = e.rot_threads;
+        if ((e.f64 != 0 && e.f64 != 1) || e.n_max < 1 || (e.block != 16 && e.block != 32) ||
+            (rt != 64 && rt != 128 && rt != 256 && rt != 512 && rt != 1024) ||
+            e.chunk_wgs < 64 || e.chunk_wgs > 4096)
+            return set_err(EA_EINVAL, "tuning entry %d out of range", i);
+        for (int j = 0; j < i; ++j)
+            if (t[j].f64 == e.f64 && t[j].n_max == e.n_max)
+                return set_err(EA_EINVAL, "tuning entries %d and %d cover the same sizes", j, i);
+    }
+    std::sort(t.begin(), t.end(), [](const ea_tune_entry &a, const ea_tune_entry &b) {
+        return a.f64 != b.f64 ? a.f64 < b.f64 : a.n_max < b.n_max;
+    });
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.swap(t);
+    return EA_OK;
+}
+
+int mps_get_tuning(int capacity, ea_tune_entry *out) {
+    if (capacity < 0 || (capacity > 0 && !out)) return set_err(EA_EINVAL, "bad output buffer");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int n = (int)g_tune.size();
+    for (int i = 0; i < n && i < capacity; ++i) out[i] = g_tune[i];
+    return n;
+}
 
 int mps_init_product(int n_sites, int kind, int prec, int chi_max, const double *local,
                      void *hip_stream, ea_mps **out) {
@@ -39,10 +88,11 @@ int mps_init_product(int n_sites, int kind, int prec, int chi_max, const double 
     h->tau = h->f64 ? 1e-13 : 2e-6;
     h->stream = (hipStream_t)hip_stream;
     if (!h->stream) {
-        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+        const hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
             (void)hipGetLastError();
             delete h;
-            return set_err(EA_EHIP, "stream creation failed");
+            return set_err(EA_EHIP, "stream creation failed: %s", hipGetErrorString(e));
         }
         h->own_stream = true;
     }

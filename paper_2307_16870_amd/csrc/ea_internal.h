@@ -20,6 +20,11 @@ namespace ea {
 
 extern thread_local std::string g_err;
 
+// Launch shape of the three-kernel Jacobi for a factorisation of n columns
+// from the process-wide tuning table (mps_set_tuning); false if no entry
+// covers it.
+bool tune_lookup(bool f64, int n, int *block, int *rot_threads, int *wgs);
+
 inline int set_err(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -270,14 +275,19 @@ int svd_core(ea_mps *h, int m, int n) {
         return EA_OK;
     }
     const bool three = h->jkernel == 0;
-    int w = h->block > 0 ? h->block : (three ? 32 : (n <= 256 ? 8 : 16));
+    // launch shape: explicit options, else the tuning table, else built in
+    int tb = 32, trt = 0, wgs = 256;
+    const bool tuned = three && tune_lookup(h->f64, n, &tb, &trt, &wgs);
+    int w = h->block > 0 ? h->block : (three ? tb : (n <= 256 ? 8 : 16));
     if (2 * w > 64) w = 32;
     const int ncmax = 2 * w <= 16 ? 16 : (2 * w <= 32 ? 32 : 64);
-    const int rot_threads = h->rot_threads > 0 ? h->rot_threads : (2 * w <= 32 ? 512 : 1024);
+    const int rot_threads = h->rot_threads > 0 ? h->rot_threads
+                            : (tuned && h->block == 0) ? trt
+                                                       : (2 * w <= 32 ? 512 : 1024);
     int nb = (n + w - 1) / w;
     nb += nb & 1;
     if (three) {
-        TRY(ensure(h, h->jpart, h->csz * jacobi_round3_partial_elems(m, n, w)));
+        TRY(ensure(h, h->jpart, h->csz * jacobi_round3_partial_elems(m, n, w, wgs)));
         TRY(ensure(h, h->jmat, h->csz * jacobi_round3_j_elems(n, w)));
         TRY(ensure(h, h->jflag, sizeof(int) * (nb / 2 + 1)));
         if (h->jskip) {
@@ -299,7 +309,7 @@ int svd_core(ea_mps *h, int m, int n) {
                     ProfScope ps(h, EA_K_JGRAM, 0.0, c * m * (double)n);
                     launch_jacobi_part<T>(0, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          stamp, rot_threads, h->stream);
+                                          stamp, rot_threads, wgs, h->stream);
                 }
                 {
                     // per block pair: the Hermitian Gram matrix (upper triangle) in,
@@ -308,13 +318,13 @@ int svd_core(ea_mps *h, int m, int n) {
                     ProfScope ps(h, EA_K_JROT, 0.0, c * (nb / 2) * (ncd * (ncd + 1) / 2 + ncd * ncd));
                     launch_jacobi_part<T>(1, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          stamp, rot_threads, h->stream);
+                                          stamp, rot_threads, wgs, h->stream);
                 }
                 {
                     ProfScope ps(h, EA_K_JAPPLY, 0.0, 2.0 * c * (m + n) * (double)n);
                     launch_jacobi_part<T>(2, h->W.p, m, h->V.p, n, w, nb, rnd, tol, h->inner_round,
                                           inter, h->jpart.p, h->jmat.p, (int *)h->jflag.p, counter,
-                                          stamp, rot_threads, h->stream);
+                                          stamp, rot_threads, wgs, h->stream);
                 }
             } else {
                 // algorithmic work of one round: every column block pair forms its

@@ -134,14 +134,16 @@ void launch_scale(void *x, size_t n, double re, double im, hipStream_t s);
 // rot_counter[0] += rotations, [1] += nc^2 of the pairs examined, [2] += nc^2
 // of the pairs rotated.  stamp (nullable, jacobi_stamp_ints(nb) ints, zero at
 // the start of a factorisation): change stamps that let a pair whose blocks
-// are unchanged since it was last examined be skipped.
+// are unchanged since it was last examined be skipped.  wgs: target number of
+// workgroups of the Gram and W-apply launches (row chunks x block pairs; the
+// V apply takes twice as many).
 template <typename T>
 void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
                         double tol, int inner_max, int inter, void *partial, void *J,
-                        int *rotflag, int *rot_counter, int *stamp, int rot_threads,
+                        int *rotflag, int *rot_counter, int *stamp, int rot_threads, int wgs,
                         hipStream_t s);
 inline size_t jacobi_stamp_ints(int nb) { return (size_t)nb + (size_t)(nb - 1) * nb; }
-size_t jacobi_round3_partial_elems(int m, int n, int w);
+size_t jacobi_round3_partial_elems(int m, int n, int w, int wgs);
 size_t jacobi_round3_j_elems(int n, int w);
 
 // ---- reverse pass (k_adjoint.hip) ------------------------------------------

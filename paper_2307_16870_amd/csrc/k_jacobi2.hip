@@ -467,10 +467,10 @@ static int rows_per_chunk(int rows, int nch) {
 template <typename T, int NC>
 static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
                        double tol, int inner_max, int inter, void *partial, void *J,
-                       int *rotflag, int *rot_counter, int *stamp, int rot_threads,
+                       int *rotflag, int *rot_counter, int *stamp, int rot_threads, int wgs,
                        hipStream_t s) {
     const int npairs = nb / 2;
-    const int nchG = chunks_for(m, npairs, 256);
+    const int nchG = chunks_for(m, npairs, wgs);
     const int rpcG = rows_per_chunk(m, nchG);
     const int nchG_eff = (m + rpcG - 1) / rpcG;
     if (part == 0) {
@@ -497,8 +497,8 @@ static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, 
         else EA_JEIG(1024);
 #undef EA_JEIG
     } else {
-        const int nchW = chunks_for(m, npairs, 256), rpcW = rows_per_chunk(m, nchW);
-        const int nchV = chunks_for(n, npairs, 512), rpcV = rows_per_chunk(n, nchV);
+        const int nchW = chunks_for(m, npairs, wgs), rpcW = rows_per_chunk(m, nchW);
+        const int nchV = chunks_for(n, npairs, 2 * wgs), rpcV = rows_per_chunk(n, nchV);
         const int nW = (m + rpcW - 1) / rpcW, nV = (n + rpcV - 1) / rpcV;
         k_japply<T, NC><<<dim3(npairs, nW + nV), 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n, w, nb,
                                                             rnd, nW, rpcW, rpcV,
@@ -507,12 +507,12 @@ static void round_part(int part, void *W, int m, void *V, int n, int w, int nb, 
 }
 
 // Workspace (in complex elements) needed by launch_jacobi_round3.
-size_t jacobi_round3_partial_elems(int m, int n, int w) {
+size_t jacobi_round3_partial_elems(int m, int n, int w, int wgs) {
     const int nc = 2 * w <= 32 ? 32 : 64;
     int nb = (n + w - 1) / w;
     nb += nb & 1;
     const int npairs = nb / 2;
-    const int nchG = chunks_for(m, npairs, 256);
+    const int nchG = chunks_for(m, npairs, wgs);
     const int rpcG = rows_per_chunk(m, nchG);
     const int nchG_eff = (m + rpcG - 1) / rpcG;
     return (size_t)npairs * nchG_eff * nc * nc;
@@ -527,19 +527,19 @@ size_t jacobi_round3_j_elems(int n, int w) {
 template <typename T>
 void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb, int rnd,
                         double tol, int inner_max, int inter, void *partial, void *J,
-                        int *rotflag, int *rot_counter, int *stamp, int rot_threads,
+                        int *rotflag, int *rot_counter, int *stamp, int rot_threads, int wgs,
                         hipStream_t s) {
     if (2 * w <= 32)
         round_part<T, 32>(part, W, m, V, n, w, nb, rnd, tol, inner_max, inter, partial, J,
-                          rotflag, rot_counter, stamp, rot_threads, s);
+                          rotflag, rot_counter, stamp, rot_threads, wgs, s);
     else
         round_part<T, 64>(part, W, m, V, n, w, nb, rnd, tol, inner_max, inter, partial, J,
-                          rotflag, rot_counter, stamp, rot_threads, s);
+                          rotflag, rot_counter, stamp, rot_threads, wgs, s);
 }
 
 template void launch_jacobi_part<float>(int, void *, int, void *, int, int, int, int, double, int,
-                                        int, void *, void *, int *, int *, int *, int,
+                                        int, void *, void *, int *, int *, int *, int, int,
                                         hipStream_t);
 template void launch_jacobi_part<double>(int, void *, int, void *, int, int, int, int, double,
-                                         int, int, void *, void *, int *, int *, int *, int,
+                                         int, int, void *, void *, int *, int *, int *, int, int,
                                          hipStream_t);

@@ -54,3 +54,32 @@ def test_null_handle_and_last_error():
     assert lib.mps_init_product(4, 0, 9, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
     assert lib.mps_init_product(4, 0, 0, -1, None, None, ctypes.byref(h)) == P.EA_EINVAL
     lib.mps_free(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_tuning_table_validation_and_order():
+    """The launch-shape table is host state: validated, copied and sorted
+    without touching a device."""
+    import paper_2307_16870_amd as P
+    saved = P.mps_get_tuning()
+    try:
+        good = [{"f64": 1, "n_max": 2048, "block": 32, "rot_threads": 1024, "chunk_wgs": 256},
+                {"f64": 0, "n_max": 512, "block": 16, "rot_threads": 256, "chunk_wgs": 128},
+                {"f64": 1, "n_max": 256, "block": 16, "rot_threads": 512, "chunk_wgs": 512}]
+        P.mps_set_tuning(good)
+        got = P.mps_get_tuning()
+        assert [(e["f64"], e["n_max"]) for e in got] == [(0, 512), (1, 256), (1, 2048)]
+        assert got[2] == good[0]
+        bad = [dict(good[0], block=8), dict(good[0], rot_threads=300), dict(good[0], f64=2),
+               dict(good[0], n_max=0), dict(good[0], chunk_wgs=32), dict(good[0], chunk_wgs=8192)]
+        for e in bad:
+            with pytest.raises(P.EAError) as ei:
+                P.mps_set_tuning([e])
+            assert ei.value.code == P.EA_EINVAL
+        with pytest.raises(P.EAError):
+            P.mps_set_tuning([good[0], dict(good[0], block=16)])  # same (f64, n_max)
+        assert P.mps_get_tuning() == got  # unchanged by the rejected calls
+        P.mps_set_tuning([])
+        assert P.mps_get_tuning() == []
+    finally:
+        P.mps_set_tuning(saved)

@@ -154,6 +154,43 @@ def test_jacobi_pair_skip_circuit_bit_identical():
     assert np.array_equal(res[0][0], res[1][0])
 
 
+@pytest.mark.parametrize("block,threads,wgs", [(16, 256, 128), (32, 512, 512)])
+def test_tuning_table_launch_shape_vs_oracle(block, threads, wgs):
+    """A tuning-table entry sets the Jacobi launch shape (seen in the number
+    of Gram launches: one per round, nb - 1 rounds per sweep) and the update
+    still meets the FP64 bar against the oracle."""
+    chis = (300, 260, 333)
+    _say("case: tuning", block, threads, wgs)
+    tens = C.random_mps_tensors([1, *chis, 1], 2, seed=sum(chis))
+    G = C.haar_unitary(np.random.default_rng(5))
+    if chis not in _SINGLE_CACHE:
+        o = OracleMPS(4, "pure", keep_spectra=True)
+        o.load(tens, 1)
+        _SINGLE_CACHE[chis] = (o, o.apply_2q(1, G, 0.98))
+    o, rec = _SINGLE_CACHE[chis]
+    saved = P.mps_get_tuning()
+    try:
+        P.mps_set_tuning([{"f64": 1, "n_max": 1 << 30, "block": block, "rot_threads": threads,
+                           "chunk_wgs": wgs}])
+        with P.EAState(4, "pure", "c128") as st:
+            st.load(tens, 1)
+            st.profile(1)
+            rc, f = st.apply_2q(1, G, 0.98)
+            g = st.gate_log()[0]
+            grams = st.profile_read(P.EA_K_JGRAM)["launches"]
+            a1, a2 = st.site(1), st.site(2)
+    finally:
+        P.mps_set_tuning(saved)
+    n = min(2 * chis[0], 2 * chis[2])
+    nb = -(-n // block)
+    nb += nb & 1
+    assert grams == (nb - 1) * g["sweeps"]
+    assert g["k"] == rec.k
+    assert abs(f - rec.f) < 1e-10
+    got, ref = gauge_free_pair(a1, a2), gauge_free_pair(o.A[1], o.A[2])
+    np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
+
+
 def test_ghz_chain_gpu():
     _say("case: ghz")
     n = 10
