@@ -166,8 +166,9 @@ def cpu_baseline(prog, f_min, chi_max, n_layers, budget_s):
 def bench_batched(args, torch, C, P):
     """Independent circuits of the batched workload (N ~ U{20..80}, depth ~
     U{10..40}, capped at --max-depth, F_min = 0.99, chi <= 1024), advanced
-    together (leading small-bond layers in one device-resident launch, then
-    one batched call per layer) and, for comparison, one after the other."""
+    together (leading small-bond layers in one device-resident launch,
+    captured once in a HIP graph and replayed by each step, then one batched
+    call per layer) and, for comparison, one after the other."""
     import numpy as np
     progs = C.batched_programs(64)[: args.circuits]
     for p in progs:
@@ -177,12 +178,14 @@ def bench_batched(args, torch, C, P):
     states = [P.EAState(p.n_sites, "pure", args.prec, chi_max=1024) for p in progs]
     depth = max(len(p.layers) for p in progs)
 
+    graph = P.capture_batched(states, progs)
+
     def run_batched():
-        # leading small-bond layers of all circuits in one device-resident
-        # launch, then one batched call per remaining layer
+        # leading small-bond layers of all circuits: a replay of the captured
+        # device-resident launch; then one batched call per remaining layer
         for st in states:
             st.reset()
-        P.run_batched(states, progs, 0.99)
+        P.run_batched(states, progs, 0.99, captured=graph)
 
     def run_sequential():
         for st, p in zip(states, progs):
@@ -213,6 +216,7 @@ def bench_batched(args, torch, C, P):
         "sequential_updates_per_s": n_upd / ts, "speedup_batched_vs_sequential": ts / tb,
         "circuits_with_P_ge_0.99": int(sum(F >= 0.99 for F in Fs)),
     }
+    graph.close()
     for s in states:
         s.close()
     print(json.dumps(out), flush=True)

@@ -110,6 +110,38 @@ enum ea_option {
                                 pair in every sweep */
 };
 
+/* ---- Captured programs (HIP graph of the device-resident launch) ---- */
+
+typedef struct ea_program ea_program; /* opaque, library-owned */
+
+/* Capture the two-qubit-gate layers of n_states circuits (arguments as for
+ * mps_run_layers_batched) as one HIP graph: an upload of the states'
+ * descriptors from pinned host memory, the persistent device-resident launch
+ * of each precision present (one workgroup per state walks its layers; Sec.
+ * V-VI per gate, global/naive/nearest schedule only), and a read-back.  The
+ * layers and gates are copied to device memory owned by the program; no
+ * state is changed.  Every state needs EA_OPT_SMALL_LAYERS != 0, at most 256
+ * gates per layer, and must outlive the program.  EA_EINVAL on bad arguments
+ * or a state given twice; EA_ENOMEM; EA_EHIP if the capture fails. */
+int mps_program_capture(int n_states, ea_mps *const *hs, const int *n_layers,
+                        const int *const *layer_gates, const int *const *sites,
+                        const double *const *ops, ea_program **out);
+
+/* Replay the program on the states' current content: each state's
+ * descriptor (site pointers, bonds, centre, fidelity log, schedule, options)
+ * is refreshed on the host, then the graph runs on the first state's stream
+ * (the other states' streams are synchronised first) and the results are
+ * applied to the handles as by mps_run_layers_batched.  layers_done (may be
+ * NULL): layers each state completed; a state stops before the first layer
+ * at which one of its bonds exceeds the small limit, and the caller goes on
+ * from there.  Returns the worst status, per state in status_out (may be
+ * NULL).  Launches of one program, or of programs sharing a state, must not
+ * overlap. */
+int mps_program_launch(ea_program *p, int *layers_done, int *status_out);
+
+/* Release the program (waits for its stream).  NULL is a no-op. */
+void mps_program_free(ea_program *p);
+
 /* ---- Launch-shape tuning (written by the package's autotuner) ---- */
 
 /* One entry of the process-wide tuning table of the three-kernel Jacobi. */

@@ -6,7 +6,7 @@ the work; this package binds it (``_binding``) and offers a small driver
 """
 from ._binding import *  # noqa: F401,F403
 from ._binding import SYMBOLS, LIB_PATH, EAError  # noqa: F401
-from .driver import EAState, run_batched  # noqa: F401
+from .driver import EAState, capture_batched, run_batched  # noqa: F401
 
 # Jacobi launch shapes chosen by the autotuner (``autotune.py``) for this
 # GPU, if present; EA_MPS_TUNING names another table, or "none" for the

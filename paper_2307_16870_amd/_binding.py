@@ -32,7 +32,8 @@ SYMBOLS = [
     "mps_to_statevector", "mps_bond_dims", "mps_center", "mps_gate_log", "mps_load",
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
     "mps_apply_layer_batched", "mps_run_layers_batched", "mps_energy_grad", "ea_last_error",
-    "mps_set_tuning", "mps_get_tuning",
+    "mps_set_tuning", "mps_get_tuning", "mps_program_capture", "mps_program_launch",
+    "mps_program_free",
 ]
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
@@ -103,6 +104,10 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_energy_grad": (I, [P, I, ct.POINTER(DOp), dp, I, I, ip, ip, dp, dp, D, D, dp, dp, dp]),
         "ea_last_error": (ct.c_char_p, []),
         "mps_set_tuning": (I, [I, ct.POINTER(TuneEntry)]),
+        "mps_program_capture": (I, [I, ct.POINTER(P), ip, ct.POINTER(ip), ct.POINTER(ip),
+                                    ct.POINTER(dp), ct.POINTER(P)]),
+        "mps_program_launch": (I, [P, ip, ip]),
+        "mps_program_free": (None, [P]),
         "mps_get_tuning": (I, [I, ct.POINTER(TuneEntry)]),
     }
     for name, (res, args) in sig.items():
@@ -314,11 +319,9 @@ def mps_apply_layer_batched(handles, sites_list, ops_list, budgets_list=None):
     return rc, st.tolist(), fs
 
 
-def mps_run_layers_batched(handles, layers_list):
-    """Leading layers of every state in one device-resident launch.
-    ``layers_list[b]`` is a list of layers, each a list of (site, 4x4 or 16x16
-    operator).  Returns (worst status, per-state statuses, per-state number
-    of layers applied)."""
+def _layer_arrays(handles, layers_list):
+    """ctypes arrays of a multi-circuit layer program (and the numpy arrays
+    they point into, which the caller keeps alive)."""
     nb = len(handles)
     hs = (ct.c_void_p * nb)(*[h.value if isinstance(h, ct.c_void_p) else h for h in handles])
     keep = []
@@ -340,11 +343,63 @@ def mps_run_layers_batched(handles, layers_list):
         gp[b] = _ip(counts)
         sp[b] = _ip(sites)
         op[b] = _dp(o)
+    return hs, nl, gp, sp, op, keep
+
+
+def mps_run_layers_batched(handles, layers_list):
+    """Leading layers of every state in one device-resident launch.
+    ``layers_list[b]`` is a list of layers, each a list of (site, 4x4 or 16x16
+    operator).  Returns (worst status, per-state statuses, per-state number
+    of layers applied)."""
+    nb = len(handles)
+    hs, nl, gp, sp, op, keep = _layer_arrays(handles, layers_list)
     done = np.zeros(nb, dtype=np.int32)
     st = np.zeros(nb, dtype=np.int32)
     rc = _lib.mps_run_layers_batched(nb, hs, _ip(nl), gp, sp, op, _ip(done), _ip(st))
     _chk(rc)
     return rc, st.tolist(), done.tolist()
+
+
+class Program:
+    """A captured multi-circuit layer program (``mps_program_capture``)."""
+
+    def __init__(self, ptr, n_states):
+        self.ptr, self.n = ptr, n_states
+
+    def close(self):
+        if self.ptr:
+            _lib.mps_program_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mps_program_capture(handles, layers_list):
+    """Capture the layers of every state (as for mps_run_layers_batched) as
+    one replayable HIP graph; returns a Program."""
+    hs, nl, gp, sp, op, keep = _layer_arrays(handles, layers_list)
+    out = ct.c_void_p()
+    _chk(_lib.mps_program_capture(len(handles), hs, _ip(nl), gp, sp, op, ct.byref(out)))
+    return Program(out, len(handles))
+
+
+def mps_program_launch(prog):
+    """Replay a Program on its states' current content.  Returns (worst
+    status, per-state statuses, per-state number of layers applied)."""
+    done = np.zeros(prog.n, dtype=np.int32)
+    st = np.zeros(prog.n, dtype=np.int32)
+    rc = _lib.mps_program_launch(prog.ptr, _ip(done), _ip(st))
+    _chk(rc)
+    return rc, st.tolist(), done.tolist()
+
+
+def mps_program_free(prog):
+    """Release a Program (also done when it is garbage-collected)."""
+    prog.close()
 
 
 def make_dops(ops):

@@ -305,24 +305,74 @@ struct SmallJob {
     int layers_done = 0;
 };
 
-// Upload one state's layers and fill its descriptor (host copy).
-template <typename T>
-int small_prepare(ea_mps *h, const SmallJob &job, SmallDesc<T> &D) {
-    const int d = h->d, n_layers = (int)job.off.size() - 1, total = job.off.back();
+// Grow every site buffer to the small-path capacity, keeping its tensor, and
+// size the state's scratch (synchronises the state's stream).
+int small_grow_sites(ea_mps *h) {
     const size_t cap = SM_ELEMS;
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    for (int i = 0; i < h->n; ++i) {  // grow the site buffers, keeping their tensors
+    for (int i = 0; i < h->n; ++i) {
         if (h->site[i].bytes >= h->csz * cap) continue;
         DevBuf nb;
         TRY(ensure(h, nb, h->csz * cap));
-        const size_t used = h->csz * (size_t)h->bond[i] * d * h->bond[i + 1];
+        const size_t used = h->csz * (size_t)h->bond[i] * h->d * h->bond[i + 1];
         if (used > 0 && h->site[i].p)
             HIPCHK(h, hipMemcpy(nb.p, h->site[i].p, used, hipMemcpyDeviceToDevice));
         free_buf(h->site[i]);
         h->site[i] = nb;
     }
+    return ensure(h, h->sm_scratch, small_scratch_bytes(h->csz));
+}
+
+// The state's scalars in a small-path descriptor (pointers are the caller's).
+template <typename T>
+void small_fill_scalars(const ea_mps *h, int total, int n_layers, SmallDesc<T> &D) {
+    D.tau = h->tau;
+    D.tol_user = h->tol;
+    D.f_min = h->f_min;
+    D.lnP = h->lnP;
+    D.lnS = h->lnS;
+    D.n_total = h->n_total;
+    D.g = h->g;
+    D.n = h->n;
+    D.d = h->d;
+    D.kind = h->kind;
+    D.n_gates = total;
+    D.n_layers = n_layers;
+    D.lim = h->small_cols / h->d;
+    D.center = h->center;
+    D.chi_max = h->chi_max;
+    D.max_sweeps = h->max_sweeps;
+    D.inner = h->inner_max;
+    D.has_sched = h->has_sched ? 1 : 0;
+    D.strategy = h->strategy;
+    D.reorth = h->reorth ? 1 : 0;
+}
+
+// Apply a finished descriptor's results to the handle: records, bonds,
+// centre, fidelity and scale logs, gate counter.  Returns the state's status.
+template <typename T>
+int small_apply_results(ea_mps *h, const SmallDesc<T> &D, const int *bond,
+                        const ea_gate_record *recs) {
+    std::copy(bond, bond + h->n + 1, h->bond.begin());
+    for (int r = 0; r < D.n_done; ++r) h->log.push_back(recs[r]);
+    h->center = D.center;
+    h->lnP = D.lnP;
+    h->lnS = D.lnS;
+    h->g = D.g;
+    if (D.status < 0)
+        return set_err(D.status, "the operator annihilates the state (all singular values 0)");
+    int rc = EA_OK;
+    if (D.n_noconv > 0) rc = std::max(rc, (int)EA_WARN_NOCONV);
+    if (D.n_capped > 0) rc = std::max(rc, (int)EA_WARN_CAPPED);
+    return rc;
+}
+
+// Upload one state's layers and fill its descriptor (host copy).
+template <typename T>
+int small_prepare(ea_mps *h, const SmallJob &job, SmallDesc<T> &D) {
+    const int d = h->d, n_layers = (int)job.off.size() - 1, total = job.off.back();
+    TRY(small_grow_sites(h));
     const size_t nop = (size_t)d * d * d * d;
-    TRY(ensure(h, h->sm_scratch, small_scratch_bytes(h->csz)));
     TRY(ensure(h, h->sm_sites, sizeof(void *) * h->n));
     TRY(ensure(h, h->sm_bond, sizeof(int) * (h->n + 1)));
     TRY(ensure(h, h->sm_loff, sizeof(int) * (n_layers + 1)));
@@ -357,26 +407,7 @@ int small_prepare(ea_mps *h, const SmallJob &job, SmallDesc<T> &D) {
     D.budget = job.budgets ? (const double *)h->sm_budget.p : nullptr;
     D.log = (ea_gate_record *)h->sm_log.p;
     D.fout = job.f_out ? (double *)h->sm_fout.p : nullptr;
-    D.tau = h->tau;
-    D.tol_user = h->tol;
-    D.f_min = h->f_min;
-    D.lnP = h->lnP;
-    D.lnS = h->lnS;
-    D.n_total = h->n_total;
-    D.g = h->g;
-    D.n = h->n;
-    D.d = d;
-    D.kind = h->kind;
-    D.n_gates = total;
-    D.n_layers = n_layers;
-    D.lim = h->small_cols / d;
-    D.center = h->center;
-    D.chi_max = h->chi_max;
-    D.max_sweeps = h->max_sweeps;
-    D.inner = h->inner_max;
-    D.has_sched = h->has_sched ? 1 : 0;
-    D.strategy = h->strategy;
-    D.reorth = h->reorth ? 1 : 0;
+    small_fill_scalars(h, total, n_layers, D);
     return EA_OK;
 }
 
@@ -392,18 +423,9 @@ int small_finish(ea_mps *h, const SmallDesc<T> &D, SmallJob &job) {
     if (job.f_out && D.n_gates > 0)
         HIPCHK(h, hipMemcpy(job.f_out, h->sm_fout.p, sizeof(double) * D.n_gates,
                             hipMemcpyDeviceToHost));
-    for (auto &r : recs) h->log.push_back(r);
-    h->center = D.center;
-    h->lnP = D.lnP;
-    h->lnS = D.lnS;
-    h->g = D.g;
     job.layers_done = D.layers_done;
-    if (D.status < 0)
-        return set_err(D.status, "the operator annihilates the state (all singular values 0)");
-    int rc = EA_OK;
-    if (D.n_noconv > 0) rc = std::max(rc, (int)EA_WARN_NOCONV);
-    if (D.n_capped > 0) rc = std::max(rc, (int)EA_WARN_CAPPED);
-    return rc;
+    const std::vector<int> bond(h->bond);
+    return small_apply_results<T>(h, D, bond.data(), recs.data());
 }
 
 // All jobs of one precision in one launch (one workgroup per state).
@@ -765,6 +787,245 @@ int mps_profile_read(ea_mps *h, int family, double *ms_timed, long *launches, do
     if (flops) *flops = h->prof_flops[family];
     if (bytes) *bytes = h->prof_bytes[family];
     return EA_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Captured programs: the device-resident small-bond launch of many circuits
+// as one replayable HIP graph
+// ============================================================================
+struct ea_program {
+    std::vector<ea_mps *> hs;
+    std::vector<int> f64, slot, total;        // per state
+    std::vector<std::vector<int>> off;        // per state: layer offsets
+    std::vector<void *> loff, gsite, gmat, log;  // per state, device, owned
+    // staging block (pinned in, device, pinned out) with the same layout:
+    // FP32 descriptors | FP64 descriptors | per state: site pointers, bonds
+    size_t at_d32 = 0, at_d64 = 0, bytes = 0;
+    std::vector<size_t> at_ptr, at_bond;
+    int n32 = 0, n64 = 0;
+    char *in = nullptr, *out = nullptr;
+    void *dev = nullptr;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void program_release(ea_program *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (auto *v : {&p->loff, &p->gsite, &p->gmat, &p->log})
+        for (void *q : *v)
+            if (q) (void)hipFree(q);
+    if (p->dev) (void)hipFree(p->dev);
+    if (p->in) (void)hipHostFree(p->in);
+    if (p->out) (void)hipHostFree(p->out);
+    delete p;
+}
+
+int dev_upload(void **dst, const void *src, size_t bytes) {
+    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return set_err(EA_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    }
+    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return set_err(EA_EHIP, "program upload failed");
+    return EA_OK;
+}
+
+// The descriptor of state b for the next replay, in the pinned block.
+template <typename T>
+int program_stage(ea_program *p, int b) {
+    ea_mps *h = p->hs[b];
+    TRY(small_grow_sites(h));
+    void **ptrs = (void **)(p->in + p->at_ptr[b]);
+    for (int i = 0; i < h->n; ++i) ptrs[i] = h->site[i].p;
+    std::copy(h->bond.begin(), h->bond.end(), (int *)(p->in + p->at_bond[b]));
+    const size_t at = (f64_of<T>() ? p->at_d64 : p->at_d32) + sizeof(SmallDesc<T>) * p->slot[b];
+    SmallDesc<T> D{};
+    D.site = (cx<T> *const *)((char *)p->dev + p->at_ptr[b]);
+    D.bond = (int *)((char *)p->dev + p->at_bond[b]);
+    D.scratch = (cx<T> *)h->sm_scratch.p;
+    D.layer_off = (const int *)p->loff[b];
+    D.gsite = (const int *)p->gsite[b];
+    D.gmat = (const cx<T> *)p->gmat[b];
+    D.budget = nullptr;
+    D.log = (ea_gate_record *)p->log[b];
+    D.fout = nullptr;
+    small_fill_scalars(h, p->total[b], (int)p->off[b].size() - 1, D);
+    std::memcpy(p->in + at, &D, sizeof D);
+    return EA_OK;
+}
+
+// Results of state b after a replay; returns its status.
+template <typename T>
+int program_finish(ea_program *p, int b, int *layers_done) {
+    ea_mps *h = p->hs[b];
+    SmallDesc<T> D;
+    std::memcpy(&D, p->out + (f64_of<T>() ? p->at_d64 : p->at_d32) + sizeof(D) * p->slot[b],
+                sizeof D);
+    std::vector<ea_gate_record> recs(std::max(0, D.n_done));
+    if (D.n_done > 0)
+        HIPCHK(h, hipMemcpy(recs.data(), p->log[b], sizeof(ea_gate_record) * D.n_done,
+                            hipMemcpyDeviceToHost));
+    *layers_done = D.layers_done;
+    return small_apply_results<T>(h, D, (const int *)(p->out + p->at_bond[b]), recs.data());
+}
+
+}  // namespace
+
+extern "C" {
+
+int mps_program_capture(int n_states, ea_mps *const *hs, const int *n_layers,
+                        const int *const *layer_gates, const int *const *sites,
+                        const double *const *ops, ea_program **out) {
+    if (!out) return set_err(EA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_states < 1) return set_err(EA_EINVAL, "n_states < 1");
+    if (!hs || !n_layers || !layer_gates || !sites || !ops)
+        return set_err(EA_EINVAL, "null argument");
+    for (int b = 0; b < n_states; ++b) {
+        TRY(check(hs[b]));
+        for (int c = 0; c < b; ++c)
+            if (hs[c] == hs[b]) return set_err(EA_EINVAL, "a state appears twice in the program");
+        if (n_layers[b] < 0) return set_err(EA_EINVAL, "n_layers < 0");
+        if (hs[b]->small_cols == 0)
+            return set_err(EA_EINVAL, "state %d has device-resident layers switched off", b);
+    }
+    ea_program *p = new ea_program();
+    auto bail = [&](int rc) {
+        program_release(p);
+        return rc;
+    };
+    p->hs.assign(hs, hs + n_states);
+    p->f64.resize(n_states);
+    p->slot.resize(n_states);
+    p->total.resize(n_states);
+    p->off.resize(n_states);
+    p->loff.assign(n_states, nullptr);
+    p->gsite.assign(n_states, nullptr);
+    p->gmat.assign(n_states, nullptr);
+    p->log.assign(n_states, nullptr);
+    for (int b = 0; b < n_states; ++b) {
+        ea_mps *h = hs[b];
+        const size_t nop = (size_t)h->d * h->d * h->d * h->d;
+        std::vector<int> &off = p->off[b];
+        off.assign(1, 0);
+        for (int L = 0; L < n_layers[b]; ++L) {
+            const int ng = layer_gates[b][L];
+            if (ng < 0 || ng > SM_GATES)
+                return bail(set_err(EA_EINVAL, "state %d layer %d: %d gates", b, L, ng));
+            TRY_OR(bail, validate_layer(h, ng, sites[b] + off.back(), ops[b] + 2 * nop * off.back(),
+                                        nullptr, nullptr, nullptr));
+            off.push_back(off.back() + ng);
+        }
+        const int total = off.back();
+        p->total[b] = total;
+        p->f64[b] = h->f64 ? 1 : 0;
+        p->slot[b] = h->f64 ? p->n64++ : p->n32++;
+        TRY_OR(bail, dev_upload(&p->loff[b], off.data(), sizeof(int) * off.size()));
+        TRY_OR(bail, dev_upload(&p->gsite[b], sites[b], sizeof(int) * total));
+        const size_t ne = 2 * nop * total;
+        if (h->f64) {
+            TRY_OR(bail, dev_upload(&p->gmat[b], ops[b], sizeof(double) * ne));
+        } else {
+            std::vector<float> g(ne);
+            for (size_t e = 0; e < ne; ++e) g[e] = (float)ops[b][e];
+            TRY_OR(bail, dev_upload(&p->gmat[b], g.data(), sizeof(float) * ne));
+        }
+        std::vector<char> zero(sizeof(ea_gate_record) * std::max(1, total), 0);
+        TRY_OR(bail, dev_upload(&p->log[b], zero.data(), zero.size()));
+    }
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    p->at_d32 = 0;
+    p->at_d64 = align(sizeof(SmallDesc<float>) * p->n32);
+    size_t at = align(p->at_d64 + sizeof(SmallDesc<double>) * p->n64);
+    p->at_ptr.resize(n_states);
+    p->at_bond.resize(n_states);
+    for (int b = 0; b < n_states; ++b) {
+        p->at_ptr[b] = at;
+        at = align(at + sizeof(void *) * hs[b]->n);
+        p->at_bond[b] = at;
+        at = align(at + sizeof(int) * (hs[b]->n + 1));
+    }
+    p->bytes = at;
+    if (hipHostMalloc((void **)&p->in, p->bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->out, p->bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&p->dev, p->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(set_err(EA_ENOMEM, "program staging (%zu bytes) failed", p->bytes));
+    }
+    std::memset(p->in, 0, p->bytes);
+    std::memset(p->out, 0, p->bytes);
+    // capture: staged descriptors in, one persistent launch per precision,
+    // results out (no memset nodes)
+    p->stream = hs[0]->stream;
+    for (int b = 0; b < n_states; ++b) HIPCHK(hs[b], hipStreamSynchronize(hs[b]->stream));
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->dev, p->in, p->bytes, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess && p->n32)
+        launch_layer_small<float>((SmallDesc<float> *)((char *)p->dev + p->at_d32), p->n32,
+                                  p->stream);
+    if (e == hipSuccess && p->n64)
+        launch_layer_small<double>((SmallDesc<double> *)((char *)p->dev + p->at_d64), p->n64,
+                                   p->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->out, p->dev, p->bytes, hipMemcpyDeviceToHost, p->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+    p->graph = g;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(set_err(EA_EHIP, "graph capture failed: %s", hipGetErrorString(e)));
+    }
+    *out = p;
+    return EA_OK;
+}
+
+int mps_program_launch(ea_program *p, int *layers_done, int *status_out) {
+    if (!p || !p->exec) return set_err(EA_EINVAL, "null program");
+    const int n_states = (int)p->hs.size();
+    for (int b = 0; b < n_states; ++b) TRY(check(p->hs[b]));
+    std::vector<int> rc(n_states, EA_OK);
+    std::vector<std::string> err(n_states);
+    for (int b = 0; b < n_states; ++b) {
+        const int r = p->f64[b] ? program_stage<double>(p, b) : program_stage<float>(p, b);
+        if (r < 0) return r;  // nothing launched: the states are unchanged
+    }
+    hipError_t e = hipGraphLaunch(p->exec, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        for (ea_mps *h : p->hs) h->poisoned = true;
+        return set_err(EA_EHIP, "program launch failed: %s", hipGetErrorString(e));
+    }
+    int worst = EA_OK, worst_b = -1;
+    for (int b = 0; b < n_states; ++b) {
+        int done = 0;
+        rc[b] = p->f64[b] ? program_finish<double>(p, b, &done) : program_finish<float>(p, b, &done);
+        if (rc[b] != EA_OK) err[b] = g_err;
+        if (layers_done) layers_done[b] = done;
+        if (status_out) status_out[b] = rc[b];
+        if ((rc[b] < 0 && (worst >= 0 || rc[b] < worst)) || (worst >= 0 && rc[b] > worst)) {
+            worst = rc[b];
+            worst_b = b;
+        }
+    }
+    if (worst_b >= 0) set_err(worst, "state %d: %s", worst_b, err[worst_b].c_str());
+    return worst;
+}
+
+void mps_program_free(ea_program *p) {
+    if (p && p->stream) (void)hipStreamSynchronize(p->stream);
+    program_release(p);
 }
 
 }  // extern "C"

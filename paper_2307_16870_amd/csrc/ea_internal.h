@@ -119,6 +119,18 @@ namespace ea {
         if (rc_ < 0) return rc_;   \
     } while (0)
 
+// As TRY, returning fail(status) instead (clean-up on the error path).
+#define TRY_OR(fail, x)                \
+    do {                               \
+        int rc_ = (x);                 \
+        if (rc_ < 0) return fail(rc_); \
+    } while (0)
+
+template <typename T>
+constexpr bool f64_of() {
+    return sizeof(T) == 8;
+}
+
 inline hipEvent_t ev_get(ea_mps *h) {
     if (!h->prof_pool.empty()) {
         hipEvent_t e = h->prof_pool.back();

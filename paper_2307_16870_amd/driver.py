@@ -114,18 +114,30 @@ class EAState:
                 self.warnings += 1
 
 
-def run_batched(states, programs, f_min=1.0, strategy=B.EA_GLOBAL, persistent=True):
+def capture_batched(states, programs):
+    """Capture the leading device-resident launch of ``run_batched`` for these
+    states and programs as a replayable HIP graph (``mps_program_capture``)."""
+    layers = [[[(op.site, op.mat) for op in layer] for layer in p.layers] for p in programs]
+    return B.mps_program_capture([s.h for s in states], layers)
+
+
+def run_batched(states, programs, f_min=1.0, strategy=B.EA_GLOBAL, persistent=True,
+                captured=None):
     """Advance independent states through their programs together.  With
     ``persistent`` the leading small-bond layers of all states run in one
-    device-resident launch (``mps_run_layers_batched``); then every remaining
-    layer is one ``mps_apply_layer_batched`` call over the states that still
-    have it.  Programs must hold two-qubit gates only.  Returns the worst
-    status seen."""
+    device-resident launch (``mps_run_layers_batched``, or a replay of
+    ``captured`` from ``capture_batched`` on the same states and programs);
+    then every remaining layer is one ``mps_apply_layer_batched`` call over
+    the states that still have it.  Programs must hold two-qubit gates only.
+    Returns the worst status seen."""
     for st, p in zip(states, programs):
         st.set_schedule(f_min, max(1, p.n_2q), strategy)
     done = [0] * len(states)
     worst = 0
-    if persistent:
+    if captured is not None:
+        rc, _, done = B.mps_program_launch(captured)
+        worst = max(worst, rc)
+    elif persistent:
         layers = [[[(op.site, op.mat) for op in layer] for layer in p.layers] for p in programs]
         rc, _, done = B.mps_run_layers_batched([s.h for s in states], layers)
         worst = max(worst, rc)

@@ -170,3 +170,25 @@ def test_run_batched_driver():
         st.close()
         psi_h, _, _, _ = _run(p, "c128", 0.99, 0)
         np.testing.assert_allclose(psi, psi_h, atol=1e-10)
+
+
+def test_run_batched_driver_with_captured_program():
+    """The driver's replay of a captured program equals its eager launch."""
+    progs = [C.brickwork_program(12, 9, 950 + b) for b in range(4)]
+    ref = []
+    for b, p in enumerate(progs):
+        with P.EAState(p.n_sites, "pure", "c128") as st:
+            P.run_batched([st], [p], 0.99)
+            ref.append(st.statevector())
+    states = [P.EAState(p.n_sites, "pure", "c128") for p in progs]
+    graph = P.capture_batched(states, progs)
+    for _ in range(2):
+        for st in states:
+            st.reset()
+        P.run_batched(states, progs, 0.99, captured=graph)
+        for st, r in zip(states, ref):
+            np.testing.assert_allclose(st.statevector(), r, atol=1e-12)
+    graph.close()
+    for st in states:
+        st.close()
+
