@@ -103,11 +103,17 @@ enum ea_option {
                                 device, no host synchronisation between its gates;
                                 mps_apply_layer and mps_apply_layer_batched, where all
                                 such states share one launch); 0: host-orchestrated */
-    EA_OPT_JACOBI_SKIP = 11  /* three-kernel Jacobi: 1 (default) skips a column block pair
+    EA_OPT_JACOBI_SKIP = 11, /* three-kernel Jacobi: 1 (default) skips a column block pair
                                 whose two blocks are unchanged since the pair was last
                                 examined (it would find the same Gram matrix and no
                                 rotation, so results are bit-identical); 0 examines every
                                 pair in every sweep */
+    EA_OPT_QR_PRECOND = 12   /* w > 0: a factorisation of at least w columns on the
+                                three-kernel Jacobi first takes the Householder QR of its
+                                matrix (Theta = Q R, panels on one workgroup each, trailing
+                                updates and products with Q as rocBLAS GEMMs) and runs the
+                                Jacobi on R^H, whose columns are nearer orthogonal (fewer
+                                sweeps); the SVD of Theta is then (Q V_x) S U_x^H.  0: off */
 };
 
 /* ---- Captured programs (HIP graph of the device-resident launch) ---- */
@@ -332,7 +338,8 @@ enum ea_kfamily {
     EA_K_GEMM = 9,         /* absorb products (centre moves, chain contraction) */
     EA_K_OTHER = 10,
     EA_K_MOVE = 11,        /* whole centre moves (overlaps the families above) */
-    EA_K_COUNT = 12
+    EA_K_QR = 12,          /* QR preconditioning: panels, trailing updates, Q products */
+    EA_K_COUNT = 13
 };
 
 /* every >= 1: reset the counters and start counting every kernel launch of

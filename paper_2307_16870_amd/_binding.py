@@ -24,7 +24,7 @@ EA_EINVAL, EA_ERANGE, EA_ENOMEM, EA_EHIP, EA_ETOOBIG = -1, -2, -3, -4, -5
 EA_NAIVE, EA_GLOBAL, EA_NEAREST = 0, 1, 2
 EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
 EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL, EA_OPT_ROT_THREADS, EA_OPT_REORTH = 5, 6, 7, 8
-EA_OPT_JACOBI_ORDER, EA_OPT_SMALL_LAYERS, EA_OPT_JACOBI_SKIP = 9, 10, 11
+EA_OPT_JACOBI_ORDER, EA_OPT_SMALL_LAYERS, EA_OPT_JACOBI_SKIP, EA_OPT_QR_PRECOND = 9, 10, 11, 12
 
 SYMBOLS = [
     "mps_init_product", "mps_free", "mps_set_option", "mps_set_schedule", "mps_apply_1q",
@@ -37,10 +37,10 @@ SYMBOLS = [
 ]
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
-                  "jacobi_small", "norms", "trunc", "gather", "gemm", "other", "centre_move"]
+                  "jacobi_small", "norms", "trunc", "gather", "gemm", "other", "centre_move", "qr"]
 (EA_K_THETA, EA_K_JGRAM, EA_K_JROT, EA_K_JAPPLY, EA_K_JFUSED, EA_K_JSMALL, EA_K_NORMS,
- EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_MOVE) = range(12)
-EA_K_COUNT = 12
+ EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_MOVE, EA_K_QR) = range(13)
+EA_K_COUNT = 13
 
 
 class EAError(RuntimeError):

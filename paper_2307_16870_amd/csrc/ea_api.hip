@@ -151,7 +151,7 @@ void mps_free(ea_mps *h) {
     h->adj = nullptr;
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
     for (auto &b : h->site) free_buf(b);
-    DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->jstamp, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
+    DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->jstamp, &h->qr_a, &h->qr_v, &h->qr_t, &h->qr_tau, &h->qr_y, &h->qr_z, &h->qr_r, &h->qr_s, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
                       &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_loff, &h->sm_gsite,
                       &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs};
@@ -160,6 +160,7 @@ void mps_free(ea_mps *h) {
     if (h->rec_host) (void)hipHostFree(h->rec_host);
     if (h->int_host) (void)hipHostFree(h->int_host);
     if (h->dbl_host) (void)hipHostFree(h->dbl_host);
+    if (h->blas) (void)rocblas_destroy_handle(h->blas);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -207,6 +208,10 @@ int mps_set_option(ea_mps *h, int option, double value) {
     case EA_OPT_JACOBI_ORDER:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi order must be 0 or 1");
         h->jorder = (int)value;
+        return EA_OK;
+    case EA_OPT_QR_PRECOND:
+        if (!(value >= 0) || value > 4096) return set_err(EA_EINVAL, "QR width out of range");
+        h->qr_min = (int)value;
         return EA_OK;
     case EA_OPT_JACOBI_SKIP:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi skip must be 0 or 1");

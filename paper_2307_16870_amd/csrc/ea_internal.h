@@ -6,6 +6,7 @@
 #include "ea_kernels.h"
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -60,6 +61,11 @@ struct ea_mps {
     int strategy = EA_GLOBAL;
     // workspace
     ea::DevBuf jpart, jmat, jflag, jstamp;
+    // QR preconditioning: factored matrix, Householder vectors, T blocks,
+    // tau, GEMM scratch, right vectors; rocBLAS handle on the state's stream
+    ea::DevBuf qr_a, qr_v, qr_t, qr_tau, qr_y, qr_z, qr_r, qr_s;
+    rocblas_handle blas = nullptr;
+    int qr_min = 0;  // precondition factorisations of at least this many columns (0: off)
     bool jskip = true;  // skip block pairs unchanged since they were last examined
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
@@ -381,6 +387,127 @@ int svd_core(ea_mps *h, int m, int n) {
     return EA_OK;
 }
 
+// C = alpha op(A) op(B) + beta C on the state's stream (column-major;
+// op 'N' or 'C' = conjugate transpose), complex FP32 or FP64.
+template <typename T>
+int blas_gemm(ea_mps *h, char opa, char opb, int m, int n, int k, double alpha, const void *A,
+              int lda, const void *B, int ldb, double beta, void *C, int ldc) {
+    if (m <= 0 || n <= 0) return EA_OK;
+    const rocblas_operation oa = opa == 'C' ? rocblas_operation_conjugate_transpose
+                                            : rocblas_operation_none;
+    const rocblas_operation ob = opb == 'C' ? rocblas_operation_conjugate_transpose
+                                            : rocblas_operation_none;
+    rocblas_status st;
+    if constexpr (sizeof(T) == 4) {
+        const rocblas_float_complex a((float)alpha, 0.f), b((float)beta, 0.f);
+        st = rocblas_cgemm(h->blas, oa, ob, m, n, k, &a, (const rocblas_float_complex *)A, lda,
+                           (const rocblas_float_complex *)B, ldb, &b, (rocblas_float_complex *)C,
+                           ldc);
+    } else {
+        const rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
+        st = rocblas_zgemm(h->blas, oa, ob, m, n, k, &a, (const rocblas_double_complex *)A, lda,
+                           (const rocblas_double_complex *)B, ldb, &b,
+                           (rocblas_double_complex *)C, ldc);
+    }
+    if (st != rocblas_status_success) {
+        h->poisoned = true;
+        return set_err(EA_EHIP, "rocBLAS gemm failed (status %d)", (int)st);
+    }
+    return EA_OK;
+}
+
+// SVD of W (m x n, m >= n, column-major) preconditioned by its Householder QR:
+// W = Q R, one-sided Jacobi on X = R^H (X V_x = W_x = U_x S), then
+// W <- Q [V_x S; 0] = U S and V <- W_x S^-1 = the right singular vectors, so
+// the caller sees the same (W = U S, V) as from svd_core.
+template <typename T>
+int svd_precond(ea_mps *h, int m, int n) {
+    const size_t c = h->csz;
+    if (m > 4096) return set_err(EA_ETOOBIG, "QR preconditioning takes at most 4096 rows");
+    if (!h->blas) {
+        if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
+            h->blas = nullptr;
+            return set_err(EA_EHIP, "rocblas_create_handle failed");
+        }
+    }
+    if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success)
+        return set_err(EA_EHIP, "rocblas_set_stream failed");
+    constexpr int NBK_MAX = 16, OBW = 64;  // panel width <= 16; reflectors applied 64 at a time
+    const int nblk = (n + OBW - 1) / OBW;
+    TRY(ensure(h, h->qr_a, c * (size_t)m * n));
+    TRY(ensure(h, h->qr_v, c * (size_t)m * n));
+    TRY(ensure(h, h->qr_t, c * ((size_t)OBW * OBW * (nblk + 1) + NBK_MAX * NBK_MAX)));
+    TRY(ensure(h, h->qr_tau, c * (size_t)n));
+    TRY(ensure(h, h->qr_y, c * (size_t)OBW * n));
+    TRY(ensure(h, h->qr_z, c * (size_t)OBW * n));
+    TRY(ensure(h, h->qr_r, c * (size_t)n * n));
+    TRY(ensure(h, h->qr_s, sizeof(double) * n));
+    char *A = (char *)h->qr_a.p, *Vall = (char *)h->qr_v.p, *Tb = (char *)h->qr_t.p;
+    char *Tpanel = Tb + c * (size_t)OBW * OBW * nblk;  // the current panel's T
+    {
+        ProfScope ps(h, EA_K_QR, 4.0 * (4.0 * m * (double)n * n - 4.0 / 3.0 * (double)n * n * n),
+                     2.0 * c * (double)m * n);
+        HIPCHK(h, hipMemcpyAsync(A, h->W.p, c * (size_t)m * n, hipMemcpyDeviceToDevice, h->stream));
+        for (int b = 0; b < nblk; ++b) {
+            const int b0 = b * OBW, bend = std::min(n, b0 + OBW), ob = bend - b0, mb = m - b0;
+            char *Vb = Vall + c * ((size_t)b0 * m + b0);
+            // the block's reflectors are zero above their diagonal
+            HIPCHK(h, hipMemset2DAsync(Vb, c * (size_t)m, 0, c * (size_t)mb, ob, h->stream));
+            for (int j0 = b0; j0 < bend;) {
+                const int nbk = launch_qr_panel<T>(A, m, bend, j0, Vall, Tpanel, h->qr_tau.p,
+                                                   h->stream);
+                if (nbk <= 0) return set_err(EA_EINVAL, "QR panel at column %d of %d x %d", j0, m, n);
+                const int nc = std::min(nbk, bend - j0), mp = m - j0, nt = bend - j0 - nc;
+                if (nt > 0) {  // the rest of the block: A2 <- A2 - V (T^H (V^H A2))
+                    const char *V = Vall + c * ((size_t)j0 * m + j0);
+                    char *A2 = A + c * ((size_t)(j0 + nc) * m + j0);
+                    TRY(blas_gemm<T>(h, 'C', 'N', nc, nt, mp, 1.0, V, m, A2, m, 0.0, h->qr_y.p, nc));
+                    TRY(blas_gemm<T>(h, 'C', 'N', nc, nt, nc, 1.0, Tpanel, nbk, h->qr_y.p, nc, 0.0,
+                                     h->qr_z.p, nc));
+                    TRY(blas_gemm<T>(h, 'N', 'N', mp, nt, nc, -1.0, V, m, h->qr_z.p, nc, 1.0, A2, m));
+                }
+                j0 += nc;
+            }
+            // the block's T from G = V_b^H V_b, then the trailing columns
+            char *Tblk = Tb + c * (size_t)OBW * OBW * b;
+            TRY(blas_gemm<T>(h, 'C', 'N', ob, ob, mb, 1.0, Vb, m, Vb, m, 0.0, h->qr_z.p, ob));
+            launch_qr_larft<T>(h->qr_z.p, (char *)h->qr_tau.p + c * (size_t)b0, ob, Tblk, h->stream);
+            const int nt = n - bend;
+            if (nt > 0) {
+                char *A2 = A + c * ((size_t)bend * m + b0);
+                TRY(blas_gemm<T>(h, 'C', 'N', ob, nt, mb, 1.0, Vb, m, A2, m, 0.0, h->qr_y.p, ob));
+                TRY(blas_gemm<T>(h, 'C', 'N', ob, nt, ob, 1.0, Tblk, ob, h->qr_y.p, ob, 0.0,
+                                 h->qr_z.p, ob));
+                TRY(blas_gemm<T>(h, 'N', 'N', mb, nt, ob, -1.0, Vb, m, h->qr_z.p, ob, 1.0, A2, m));
+            }
+        }
+        launch_qr_rh<T>(A, m, n, h->W.p, h->stream);
+        LAUNCHCHK(h);
+    }
+    TRY(svd_core<T>(h, n, n));  // W = W_x (n x n), V = V_x
+    {
+        ProfScope ps(h, EA_K_QR, 4.0 * (4.0 * m * (double)n * n - 2.0 * (double)n * n * n),
+                     2.0 * c * (double)m * n);
+        launch_colnorms<T>(h->W.p, n, n, (double *)h->qr_s.p, h->stream);
+        launch_qr_finish<T>(h->W.p, h->V.p, (const double *)h->qr_s.p, n, h->qr_r.p, h->stream);
+        launch_qr_fill<T>(h->V.p, m, n, h->W.p, h->stream);  // W = [V_x S; 0]
+        LAUNCHCHK(h);
+        // W <- Q W = Q_1 (Q_2 (... W)): blocks in reverse, W2 -= V (T (V^H W2))
+        for (int b = nblk - 1; b >= 0; --b) {
+            const int b0 = b * OBW, ob = std::min(n, b0 + OBW) - b0, mb = m - b0;
+            const char *Vb = Vall + c * ((size_t)b0 * m + b0);
+            const char *Tblk = Tb + c * (size_t)OBW * OBW * b;
+            char *W2 = (char *)h->W.p + c * (size_t)b0;
+            TRY(blas_gemm<T>(h, 'C', 'N', ob, n, mb, 1.0, Vb, m, W2, m, 0.0, h->qr_y.p, ob));
+            TRY(blas_gemm<T>(h, 'N', 'N', ob, n, ob, 1.0, Tblk, ob, h->qr_y.p, ob, 0.0, h->qr_z.p,
+                             ob));
+            TRY(blas_gemm<T>(h, 'N', 'N', mb, n, ob, -1.0, Vb, m, h->qr_z.p, ob, 1.0, W2, m));
+        }
+        std::swap(h->V, h->qr_r);  // V = W_x S^-1
+    }
+    return EA_OK;
+}
+
 // Factor matrix X (rows x cols, currently in W as column-major after the
 // caller's copy/contraction) and read back the decision record.
 template <typename T>
@@ -388,7 +515,10 @@ int factor_and_decide(ea_mps *h, int mw, int nw, double f_t, int mode, int force
     TRY(ensure(h, h->s_raw, sizeof(double) * nw));
     TRY(ensure(h, h->s_sorted, sizeof(double) * nw));
     TRY(ensure(h, h->perm, sizeof(int) * nw));
-    TRY(svd_core<T>(h, mw, nw));
+    if (h->qr_min > 0 && nw >= h->qr_min && nw > 64 && h->jkernel == 0)
+        TRY(svd_precond<T>(h, mw, nw));
+    else
+        TRY(svd_core<T>(h, mw, nw));
     {
         ProfScope ps(h, EA_K_NORMS, 4.0 * mw * (double)nw, (double)h->csz * mw * (double)nw);
         launch_colnorms<T>(h->W.p, mw, nw, (double *)h->s_raw.p, h->stream);

@@ -144,6 +144,26 @@ void launch_jacobi_part(int part, void *W, int m, void *V, int n, int w, int nb,
                         hipStream_t s);
 inline size_t jacobi_stamp_ints(int nb) { return (size_t)nb + (size_t)(nb - 1) * nb; }
 size_t jacobi_round3_partial_elems(int m, int n, int w, int wgs);
+// ---- QR preconditioning (k_qr.hip) ----
+// Columns of the next panel for a panel of mp rows (mp <= 4096).
+int qr_panel_width(int elem_bytes, int mp);
+// Factor the panel of columns j0.. (rows j0..m-1) of A (m x n, column-major)
+// in place; writes its Householder vectors (unit lower trapezoidal) into the
+// same columns of Vall, its T (nbk x nbk, column-major) to Tout and tau[j0..].
+// Returns the panel width nbk used (columns j0 .. j0 + min(nbk, n - j0) - 1),
+// or -1 if m - j0 is outside 1..4096 or j0 >= n.
+template <typename T>
+int launch_qr_panel(void *A, int m, int n, int j0, void *Vall, void *Tout, void *tau,
+                    hipStream_t s);
+template <typename T>
+void launch_qr_rh(const void *A, int m, int n, void *X, hipStream_t s);
+template <typename T>
+void launch_qr_finish(const void *Wx, void *Vx, const double *sv, int n, void *Vr, hipStream_t s);
+template <typename T>
+void launch_qr_fill(const void *Y, int m, int n, void *C, hipStream_t s);
+// T (ob x ob) of the compact WY form of ob <= 64 reflectors from G = V^H V and tau.
+template <typename T>
+void launch_qr_larft(const void *G, const void *tau, int ob, void *Tout, hipStream_t s);
 size_t jacobi_round3_j_elems(int n, int w);
 
 // ---- reverse pass (k_adjoint.hip) ------------------------------------------

@@ -191,6 +191,57 @@ def test_tuning_table_launch_shape_vs_oracle(block, threads, wgs):
     np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("chis", [(37, 70, 45), (160, 150, 129), (300, 260, 333)])
+def test_qr_preconditioned_update_vs_oracle(chis):
+    """SVD through the Householder QR (Jacobi on R^H, left vectors Q V_x):
+    the FP64 bar against the oracle, with ragged panels and blocks."""
+    _say("case: qr preconditioned", chis)
+    tens = C.random_mps_tensors([1, *chis, 1], 2, seed=sum(chis))
+    G = C.haar_unitary(np.random.default_rng(5))
+    if chis not in _SINGLE_CACHE:
+        o = OracleMPS(4, "pure", keep_spectra=True)
+        o.load(tens, 1)
+        _SINGLE_CACHE[chis] = (o, o.apply_2q(1, G, 0.98))
+    o, rec = _SINGLE_CACHE[chis]
+    with P.EAState(4, "pure", "c128") as st:
+        st.set_option(P.EA_OPT_QR_PRECOND, 65)
+        st.load(tens, 1)
+        st.profile(1)
+        rc, f = st.apply_2q(1, G, 0.98)
+        g = st.gate_log()[0]
+        qr_launches = st.profile_read(P.EA_K_QR)["launches"]
+        a1, a2 = st.site(1), st.site(2)
+    assert qr_launches > 0
+    assert abs(g["total"] - float(np.sum(rec.s ** 2))) < 1e-10 * g["total"]
+    assert g["k"] == rec.k
+    assert abs(f - rec.f) < 1e-10
+    got, ref = gauge_free_pair(a1, a2), gauge_free_pair(o.A[1], o.A[2])
+    np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_qr_preconditioned_circuit(prec):
+    """A 16-qubit depth-12 truncating circuit with every factorisation above
+    64 columns preconditioned, against the same circuit without."""
+    _say("case: qr preconditioned circuit", prec)
+    prog = C.brickwork_program(16, 12, 43)
+    res = []
+    for qr in (0, 65):
+        with P.EAState(prog.n_sites, "pure", prec) as st:
+            st.set_option(P.EA_OPT_SMALL_LAYERS, 0)
+            st.set_option(P.EA_OPT_QR_PRECOND, qr)
+            st.run(prog, 0.97)
+            res.append((st.statevector(), [r["k"] for r in st.gate_log()], st.fidelity_estimate()[0]))
+    (psi0, k0, F0), (psi1, k1, F1) = res
+    if prec == "c128":
+        assert k0 == k1
+        np.testing.assert_allclose(psi1, psi0, atol=1e-10)
+        assert abs(F1 - F0) < 1e-12
+    else:
+        assert np.abs(psi1 - psi0).max() < 2e-4
+        assert abs(F1 - F0) < 1e-5
+
+
 def test_ghz_chain_gpu():
     _say("case: ghz")
     n = 10
