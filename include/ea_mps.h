@@ -108,6 +108,11 @@ enum ea_option {
                                 examined (it would find the same Gram matrix and no
                                 rotation, so results are bit-identical); 0 examines every
                                 pair in every sweep */
+    EA_OPT_QR_MOVES = 13,    /* 1: centre moves of the update path by Householder QR
+                                (A_c = Q R, Q the new site, R absorbed into the neighbour;
+                                Sec. III), no rank dropped; 0: by the Jacobi SVD, dropping
+                                numerically zero singular values.  The gradient path
+                                (mps_energy_grad) always moves by SVD. */
     EA_OPT_QR_PRECOND = 12   /* w > 0: a factorisation of at least w columns on the
                                 three-kernel Jacobi first takes the Householder QR of its
                                 matrix (Theta = Q R, panels on one workgroup each, trailing

@@ -209,6 +209,10 @@ int mps_set_option(ea_mps *h, int option, double value) {
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "jacobi order must be 0 or 1");
         h->jorder = (int)value;
         return EA_OK;
+    case EA_OPT_QR_MOVES:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "QR moves must be 0 or 1");
+        h->qr_moves = value != 0;
+        return EA_OK;
     case EA_OPT_QR_PRECOND:
         if (!(value >= 0) || value > 4096) return set_err(EA_EINVAL, "QR width out of range");
         h->qr_min = (int)value;

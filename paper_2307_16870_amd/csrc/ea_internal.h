@@ -66,6 +66,7 @@ struct ea_mps {
     ea::DevBuf qr_a, qr_v, qr_t, qr_tau, qr_y, qr_z, qr_r, qr_s;
     rocblas_handle blas = nullptr;
     int qr_min = 0;  // precondition factorisations of at least this many columns (0: off)
+    bool qr_moves = false;  // centre moves of the simulation path by Householder QR
     bool jskip = true;  // skip block pairs unchanged since they were last examined
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
@@ -388,15 +389,16 @@ int svd_core(ea_mps *h, int m, int n) {
 }
 
 // C = alpha op(A) op(B) + beta C on the state's stream (column-major;
-// op 'N' or 'C' = conjugate transpose), complex FP32 or FP64.
+// op 'N', 'T' = transpose or 'C' = conjugate transpose), complex FP32 or FP64.
 template <typename T>
 int blas_gemm(ea_mps *h, char opa, char opb, int m, int n, int k, double alpha, const void *A,
               int lda, const void *B, int ldb, double beta, void *C, int ldc) {
     if (m <= 0 || n <= 0) return EA_OK;
-    const rocblas_operation oa = opa == 'C' ? rocblas_operation_conjugate_transpose
-                                            : rocblas_operation_none;
-    const rocblas_operation ob = opb == 'C' ? rocblas_operation_conjugate_transpose
-                                            : rocblas_operation_none;
+    auto op = [](char o) {
+        return o == 'C' ? rocblas_operation_conjugate_transpose
+                        : (o == 'T' ? rocblas_operation_transpose : rocblas_operation_none);
+    };
+    const rocblas_operation oa = op(opa), ob = op(opb);
     rocblas_status st;
     if constexpr (sizeof(T) == 4) {
         const rocblas_float_complex a((float)alpha, 0.f), b((float)beta, 0.f);
@@ -416,6 +418,101 @@ int blas_gemm(ea_mps *h, char opa, char opb, int m, int n, int k, double alpha, 
     return EA_OK;
 }
 
+constexpr int QR_NBK_MAX = 16, QR_OBW = 64;  // panel width <= 16; reflectors applied 64 at a time
+
+inline int blas_ready(ea_mps *h) {
+    if (!h->blas && rocblas_create_handle(&h->blas) != rocblas_status_success) {
+        h->blas = nullptr;
+        return set_err(EA_EHIP, "rocblas_create_handle failed");
+    }
+    if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success)
+        return set_err(EA_EHIP, "rocblas_set_stream failed");
+    return EA_OK;
+}
+
+// Householder QR of src (m x n, column-major, ld m; m <= 4096) with
+// k = min(m, n) reflectors: the factored matrix (R in its upper trapezoid) in
+// qr_a, the reflectors (unit lower trapezoidal) in qr_v, per 64-column block
+// the T of Q_b = I - V_b T_b V_b^H in qr_t; Q = Q_1 Q_2 ... .
+template <typename T>
+int qr_factor(ea_mps *h, const void *src, int m, int n) {
+    const size_t c = h->csz;
+    const int k = std::min(m, n), nblk = (k + QR_OBW - 1) / QR_OBW;
+    if (m > 4096) return set_err(EA_ETOOBIG, "the QR takes at most 4096 rows");
+    TRY(blas_ready(h));
+    TRY(ensure(h, h->qr_a, c * (size_t)m * n));
+    TRY(ensure(h, h->qr_v, c * (size_t)m * k));
+    TRY(ensure(h, h->qr_t, c * ((size_t)QR_OBW * QR_OBW * (nblk + 1) + QR_NBK_MAX * QR_NBK_MAX)));
+    TRY(ensure(h, h->qr_tau, c * (size_t)k));
+    TRY(ensure(h, h->qr_y, c * (size_t)QR_OBW * std::max(m, n)));
+    TRY(ensure(h, h->qr_z, c * (size_t)QR_OBW * std::max(m, n)));
+    char *A = (char *)h->qr_a.p, *Vall = (char *)h->qr_v.p, *Tb = (char *)h->qr_t.p;
+    char *Tpanel = Tb + c * (size_t)QR_OBW * QR_OBW * nblk;  // the current panel's T
+    ProfScope ps(h, EA_K_QR, 4.0 * (4.0 * m * (double)n * k - 2.0 * (double)(m + n) * k * k +
+                                    4.0 / 3.0 * (double)k * k * k),
+                 2.0 * c * (double)m * n);
+    HIPCHK(h, hipMemcpyAsync(A, src, c * (size_t)m * n, hipMemcpyDeviceToDevice, h->stream));
+    for (int b = 0; b < nblk; ++b) {
+        const int b0 = b * QR_OBW, bend = std::min(k, b0 + QR_OBW), ob = bend - b0, mb = m - b0;
+        char *Vb = Vall + c * ((size_t)b0 * m + b0);
+        // the block's reflectors are zero above their diagonal
+        HIPCHK(h, hipMemset2DAsync(Vb, c * (size_t)m, 0, c * (size_t)mb, ob, h->stream));
+        for (int j0 = b0; j0 < bend;) {
+            const int nbk = launch_qr_panel<T>(A, m, bend, j0, Vall, Tpanel, h->qr_tau.p, h->stream);
+            if (nbk <= 0) return set_err(EA_EINVAL, "QR panel at column %d of %d x %d", j0, m, n);
+            const int nc = std::min(nbk, bend - j0), mp = m - j0, nt = bend - j0 - nc;
+            if (nt > 0) {  // the rest of the block: A2 <- A2 - V (T^H (V^H A2))
+                const char *V = Vall + c * ((size_t)j0 * m + j0);
+                char *A2 = A + c * ((size_t)(j0 + nc) * m + j0);
+                TRY(blas_gemm<T>(h, 'C', 'N', nc, nt, mp, 1.0, V, m, A2, m, 0.0, h->qr_y.p, nc));
+                TRY(blas_gemm<T>(h, 'C', 'N', nc, nt, nc, 1.0, Tpanel, nbk, h->qr_y.p, nc, 0.0,
+                                 h->qr_z.p, nc));
+                TRY(blas_gemm<T>(h, 'N', 'N', mp, nt, nc, -1.0, V, m, h->qr_z.p, nc, 1.0, A2, m));
+            }
+            j0 += nc;
+        }
+        // the block's T from G = V_b^H V_b, then every column right of the block
+        char *Tblk = Tb + c * (size_t)QR_OBW * QR_OBW * b;
+        TRY(blas_gemm<T>(h, 'C', 'N', ob, ob, mb, 1.0, Vb, m, Vb, m, 0.0, h->qr_z.p, ob));
+        launch_qr_larft<T>(h->qr_z.p, (char *)h->qr_tau.p + c * (size_t)b0, ob, Tblk, h->stream);
+        const int nt = n - bend;
+        if (nt > 0) {
+            char *A2 = A + c * ((size_t)bend * m + b0);
+            TRY(blas_gemm<T>(h, 'C', 'N', ob, nt, mb, 1.0, Vb, m, A2, m, 0.0, h->qr_y.p, ob));
+            TRY(blas_gemm<T>(h, 'C', 'N', ob, nt, ob, 1.0, Tblk, ob, h->qr_y.p, ob, 0.0, h->qr_z.p,
+                             ob));
+            TRY(blas_gemm<T>(h, 'N', 'N', mb, nt, ob, -1.0, Vb, m, h->qr_z.p, ob, 1.0, A2, m));
+        }
+    }
+    LAUNCHCHK(h);
+    return EA_OK;
+}
+
+// C (m x ncols, column-major, ld m) <- Q C with the Q of the last qr_factor
+// of an m x n matrix (k = min(m, n) reflectors, applied block by block from
+// the last).
+template <typename T>
+int qr_apply_q(ea_mps *h, void *C, int m, int n, int ncols) {
+    const size_t c = h->csz;
+    const int k = std::min(m, n), nblk = (k + QR_OBW - 1) / QR_OBW;
+    TRY(ensure(h, h->qr_y, c * (size_t)QR_OBW * ncols));
+    TRY(ensure(h, h->qr_z, c * (size_t)QR_OBW * ncols));
+    ProfScope ps(h, EA_K_QR, 4.0 * (4.0 * m * (double)ncols * k - 2.0 * (double)ncols * k * k),
+                 2.0 * c * (double)m * ncols);
+    const char *Vall = (const char *)h->qr_v.p, *Tb = (const char *)h->qr_t.p;
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int b0 = b * QR_OBW, ob = std::min(k, b0 + QR_OBW) - b0, mb = m - b0;
+        const char *Vb = Vall + c * ((size_t)b0 * m + b0);
+        const char *Tblk = Tb + c * (size_t)QR_OBW * QR_OBW * b;
+        char *C2 = (char *)C + c * (size_t)b0;
+        TRY(blas_gemm<T>(h, 'C', 'N', ob, ncols, mb, 1.0, Vb, m, C2, m, 0.0, h->qr_y.p, ob));
+        TRY(blas_gemm<T>(h, 'N', 'N', ob, ncols, ob, 1.0, Tblk, ob, h->qr_y.p, ob, 0.0, h->qr_z.p,
+                         ob));
+        TRY(blas_gemm<T>(h, 'N', 'N', mb, ncols, ob, -1.0, Vb, m, h->qr_z.p, ob, 1.0, C2, m));
+    }
+    return EA_OK;
+}
+
 // SVD of W (m x n, m >= n, column-major) preconditioned by its Householder QR:
 // W = Q R, one-sided Jacobi on X = R^H (X V_x = W_x = U_x S), then
 // W <- Q [V_x S; 0] = U S and V <- W_x S^-1 = the right singular vectors, so
@@ -423,88 +520,18 @@ int blas_gemm(ea_mps *h, char opa, char opb, int m, int n, int k, double alpha, 
 template <typename T>
 int svd_precond(ea_mps *h, int m, int n) {
     const size_t c = h->csz;
-    if (m > 4096) return set_err(EA_ETOOBIG, "QR preconditioning takes at most 4096 rows");
-    if (!h->blas) {
-        if (rocblas_create_handle(&h->blas) != rocblas_status_success) {
-            h->blas = nullptr;
-            return set_err(EA_EHIP, "rocblas_create_handle failed");
-        }
-    }
-    if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success)
-        return set_err(EA_EHIP, "rocblas_set_stream failed");
-    constexpr int NBK_MAX = 16, OBW = 64;  // panel width <= 16; reflectors applied 64 at a time
-    const int nblk = (n + OBW - 1) / OBW;
-    TRY(ensure(h, h->qr_a, c * (size_t)m * n));
-    TRY(ensure(h, h->qr_v, c * (size_t)m * n));
-    TRY(ensure(h, h->qr_t, c * ((size_t)OBW * OBW * (nblk + 1) + NBK_MAX * NBK_MAX)));
-    TRY(ensure(h, h->qr_tau, c * (size_t)n));
-    TRY(ensure(h, h->qr_y, c * (size_t)OBW * n));
-    TRY(ensure(h, h->qr_z, c * (size_t)OBW * n));
+    TRY(qr_factor<T>(h, h->W.p, m, n));
+    launch_qr_rh<T>(h->qr_a.p, m, n, h->W.p, h->stream);  // W = R^H (n x n)
+    LAUNCHCHK(h);
+    TRY(svd_core<T>(h, n, n));  // W = W_x (n x n), V = V_x
     TRY(ensure(h, h->qr_r, c * (size_t)n * n));
     TRY(ensure(h, h->qr_s, sizeof(double) * n));
-    char *A = (char *)h->qr_a.p, *Vall = (char *)h->qr_v.p, *Tb = (char *)h->qr_t.p;
-    char *Tpanel = Tb + c * (size_t)OBW * OBW * nblk;  // the current panel's T
-    {
-        ProfScope ps(h, EA_K_QR, 4.0 * (4.0 * m * (double)n * n - 4.0 / 3.0 * (double)n * n * n),
-                     2.0 * c * (double)m * n);
-        HIPCHK(h, hipMemcpyAsync(A, h->W.p, c * (size_t)m * n, hipMemcpyDeviceToDevice, h->stream));
-        for (int b = 0; b < nblk; ++b) {
-            const int b0 = b * OBW, bend = std::min(n, b0 + OBW), ob = bend - b0, mb = m - b0;
-            char *Vb = Vall + c * ((size_t)b0 * m + b0);
-            // the block's reflectors are zero above their diagonal
-            HIPCHK(h, hipMemset2DAsync(Vb, c * (size_t)m, 0, c * (size_t)mb, ob, h->stream));
-            for (int j0 = b0; j0 < bend;) {
-                const int nbk = launch_qr_panel<T>(A, m, bend, j0, Vall, Tpanel, h->qr_tau.p,
-                                                   h->stream);
-                if (nbk <= 0) return set_err(EA_EINVAL, "QR panel at column %d of %d x %d", j0, m, n);
-                const int nc = std::min(nbk, bend - j0), mp = m - j0, nt = bend - j0 - nc;
-                if (nt > 0) {  // the rest of the block: A2 <- A2 - V (T^H (V^H A2))
-                    const char *V = Vall + c * ((size_t)j0 * m + j0);
-                    char *A2 = A + c * ((size_t)(j0 + nc) * m + j0);
-                    TRY(blas_gemm<T>(h, 'C', 'N', nc, nt, mp, 1.0, V, m, A2, m, 0.0, h->qr_y.p, nc));
-                    TRY(blas_gemm<T>(h, 'C', 'N', nc, nt, nc, 1.0, Tpanel, nbk, h->qr_y.p, nc, 0.0,
-                                     h->qr_z.p, nc));
-                    TRY(blas_gemm<T>(h, 'N', 'N', mp, nt, nc, -1.0, V, m, h->qr_z.p, nc, 1.0, A2, m));
-                }
-                j0 += nc;
-            }
-            // the block's T from G = V_b^H V_b, then the trailing columns
-            char *Tblk = Tb + c * (size_t)OBW * OBW * b;
-            TRY(blas_gemm<T>(h, 'C', 'N', ob, ob, mb, 1.0, Vb, m, Vb, m, 0.0, h->qr_z.p, ob));
-            launch_qr_larft<T>(h->qr_z.p, (char *)h->qr_tau.p + c * (size_t)b0, ob, Tblk, h->stream);
-            const int nt = n - bend;
-            if (nt > 0) {
-                char *A2 = A + c * ((size_t)bend * m + b0);
-                TRY(blas_gemm<T>(h, 'C', 'N', ob, nt, mb, 1.0, Vb, m, A2, m, 0.0, h->qr_y.p, ob));
-                TRY(blas_gemm<T>(h, 'C', 'N', ob, nt, ob, 1.0, Tblk, ob, h->qr_y.p, ob, 0.0,
-                                 h->qr_z.p, ob));
-                TRY(blas_gemm<T>(h, 'N', 'N', mb, nt, ob, -1.0, Vb, m, h->qr_z.p, ob, 1.0, A2, m));
-            }
-        }
-        launch_qr_rh<T>(A, m, n, h->W.p, h->stream);
-        LAUNCHCHK(h);
-    }
-    TRY(svd_core<T>(h, n, n));  // W = W_x (n x n), V = V_x
-    {
-        ProfScope ps(h, EA_K_QR, 4.0 * (4.0 * m * (double)n * n - 2.0 * (double)n * n * n),
-                     2.0 * c * (double)m * n);
-        launch_colnorms<T>(h->W.p, n, n, (double *)h->qr_s.p, h->stream);
-        launch_qr_finish<T>(h->W.p, h->V.p, (const double *)h->qr_s.p, n, h->qr_r.p, h->stream);
-        launch_qr_fill<T>(h->V.p, m, n, h->W.p, h->stream);  // W = [V_x S; 0]
-        LAUNCHCHK(h);
-        // W <- Q W = Q_1 (Q_2 (... W)): blocks in reverse, W2 -= V (T (V^H W2))
-        for (int b = nblk - 1; b >= 0; --b) {
-            const int b0 = b * OBW, ob = std::min(n, b0 + OBW) - b0, mb = m - b0;
-            const char *Vb = Vall + c * ((size_t)b0 * m + b0);
-            const char *Tblk = Tb + c * (size_t)OBW * OBW * b;
-            char *W2 = (char *)h->W.p + c * (size_t)b0;
-            TRY(blas_gemm<T>(h, 'C', 'N', ob, n, mb, 1.0, Vb, m, W2, m, 0.0, h->qr_y.p, ob));
-            TRY(blas_gemm<T>(h, 'N', 'N', ob, n, ob, 1.0, Tblk, ob, h->qr_y.p, ob, 0.0, h->qr_z.p,
-                             ob));
-            TRY(blas_gemm<T>(h, 'N', 'N', mb, n, ob, -1.0, Vb, m, h->qr_z.p, ob, 1.0, W2, m));
-        }
-        std::swap(h->V, h->qr_r);  // V = W_x S^-1
-    }
+    launch_colnorms<T>(h->W.p, n, n, (double *)h->qr_s.p, h->stream);
+    launch_qr_finish<T>(h->W.p, h->V.p, (const double *)h->qr_s.p, n, h->qr_r.p, h->stream);
+    launch_qr_fill<T>(h->V.p, m, n, h->W.p, h->stream);  // W = [V_x S; 0]
+    LAUNCHCHK(h);
+    TRY(qr_apply_q<T>(h, h->W.p, m, n, n));
+    std::swap(h->V, h->qr_r);  // V = W_x S^-1
     return EA_OK;
 }
 
@@ -674,15 +701,86 @@ int move_left(ea_mps *h) {
     return EA_OK;
 }
 
+// Centre moves by Householder QR (Sec. III: A_c = Q R, Q left-normalised,
+// R absorbed into the neighbour; no rank is dropped).  Right: A_c as
+// (chi_l d) x chi_r = Q R, A_c <- Q, A_{c+1} <- R A_{c+1}.
+template <typename T>
+int move_right_qr(ea_mps *h) {
+    const int c = h->center, d = h->d;
+    const int M = h->bond[c] * d, N = h->bond[c + 1], k = std::min(M, N);
+    const int P = d * h->bond[c + 2];
+    if (M > 4096) return set_err(EA_ETOOBIG, "bond too large for a QR centre move");
+    TRY(ensure(h, h->W, h->csz * (size_t)M * N));
+    launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, 0, h->stream);
+    TRY(qr_factor<T>(h, h->W.p, M, N));
+    TRY(ensure(h, h->X, h->csz * (size_t)k * N));
+    launch_qr_r_extract<T>(h->qr_a.p, M, k, N, 0, h->X.p, h->stream);  // R (k x N)
+    launch_qr_eye<T>(M, k, h->W.p, h->stream);
+    LAUNCHCHK(h);
+    TRY(qr_apply_q<T>(h, h->W.p, M, N, k));  // Q (M x k)
+    TRY(ensure(h, h->site[c], h->csz * (size_t)M * k));
+    TRY(ensure(h, h->spare, h->csz * (size_t)k * P));
+    {
+        ProfScope ps(h, EA_K_GEMM, 8.0 * k * (double)N * P,
+                     (double)h->csz * ((double)k * N + (double)N * P + (double)k * P));
+        launch_to_colmajor<T>(h->W.p, h->site[c].p, k, M, 0, h->stream);  // row-major (M, k)
+        // (R A_{c+1})^T = A_{c+1}^T R^T in column-major terms: row-major (k, P)
+        TRY(blas_gemm<T>(h, 'N', 'T', P, k, N, 1.0, h->site[c + 1].p, P, h->X.p, k, 0.0,
+                         h->spare.p, P));
+    }
+    LAUNCHCHK(h);
+    std::swap(h->site[c + 1], h->spare);
+    TRY(reorth<T>(h, true, h->site[c].p, M, k, h->site[c + 1].p, P));
+    h->bond[c + 1] = k;
+    h->center = c + 1;
+    return EA_OK;
+}
+
+// Left: A_c as chi_l x (d chi_r) = L Q_r through the QR of A_c^H = Q' R':
+// A_c <- Q'^H (orthonormal rows), A_{c-1} <- A_{c-1} R'^H.
+template <typename T>
+int move_left_qr(ea_mps *h) {
+    const int c = h->center, d = h->d;
+    const int M = h->bond[c], N = d * h->bond[c + 1], k = std::min(M, N);
+    const int P = h->bond[c - 1] * d;
+    if (N > 4096) return set_err(EA_ETOOBIG, "bond too large for a QR centre move");
+    TRY(ensure(h, h->W, h->csz * (size_t)M * N));
+    launch_to_colmajor<T>(h->site[c].p, h->W.p, M, N, 1, h->stream);  // A^H, N x M
+    TRY(qr_factor<T>(h, h->W.p, N, M));
+    TRY(ensure(h, h->X, h->csz * (size_t)k * M));
+    launch_qr_r_extract<T>(h->qr_a.p, N, k, M, 1, h->X.p, h->stream);  // conj(R') (k x M)
+    launch_qr_eye<T>(N, k, h->W.p, h->stream);
+    LAUNCHCHK(h);
+    TRY(qr_apply_q<T>(h, h->W.p, N, M, k));  // Q' (N x k)
+    TRY(ensure(h, h->site[c], h->csz * (size_t)k * N));
+    TRY(ensure(h, h->spare, h->csz * (size_t)P * k));
+    {
+        ProfScope ps(h, EA_K_GEMM, 8.0 * P * (double)M * k,
+                     (double)h->csz * ((double)P * M + (double)M * k + (double)P * k));
+        launch_to_colmajor<T>(h->W.p, h->site[c].p, k, N, 1, h->stream);  // Q'^H, row-major (k, N)
+        // (A_{c-1} R'^H)^T = conj(R') A_{c-1}^T in column-major terms: row-major (P, k)
+        TRY(blas_gemm<T>(h, 'N', 'N', k, P, M, 1.0, h->X.p, k, h->site[c - 1].p, M, 0.0,
+                         h->spare.p, k));
+    }
+    LAUNCHCHK(h);
+    std::swap(h->site[c - 1], h->spare);
+    TRY(reorth<T>(h, false, h->site[c].p, N, k, h->site[c - 1].p, P));
+    h->bond[c] = k;
+    h->center = c - 1;
+    return EA_OK;
+}
+
 template <typename T>
 int move_center(ea_mps *h, int j) {
     while (h->center < j) {
         ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
-        TRY(move_right<T>(h));
+        if (h->qr_moves) TRY(move_right_qr<T>(h));
+        else TRY(move_right<T>(h));
     }
     while (h->center > j) {
         ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
-        TRY(move_left<T>(h));
+        if (h->qr_moves) TRY(move_left_qr<T>(h));
+        else TRY(move_left<T>(h));
     }
     return EA_OK;
 }

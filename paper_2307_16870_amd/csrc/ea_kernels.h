@@ -161,6 +161,13 @@ template <typename T>
 void launch_qr_finish(const void *Wx, void *Vx, const double *sv, int n, void *Vr, hipStream_t s);
 template <typename T>
 void launch_qr_fill(const void *Y, int m, int n, void *C, hipStream_t s);
+// out (k x ncols) = upper trapezoid of A's first k rows (conjugated if conj_r).
+template <typename T>
+void launch_qr_r_extract(const void *A, int lda, int k, int ncols, int conj_r, void *out,
+                         hipStream_t s);
+// C (m x k) = [I_k; 0].
+template <typename T>
+void launch_qr_eye(int m, int k, void *C, hipStream_t s);
 // T (ob x ob) of the compact WY form of ob <= 64 reflectors from G = V^H V and tau.
 template <typename T>
 void launch_qr_larft(const void *G, const void *tau, int ob, void *Tout, hipStream_t s);

@@ -301,3 +301,46 @@ void launch_qr_larft(const void *G, const void *tau, int ob, void *Tout, hipStre
 }
 template void launch_qr_larft<float>(const void *, const void *, int, void *, hipStream_t);
 template void launch_qr_larft<double>(const void *, const void *, int, void *, hipStream_t);
+
+// out (k x ncols, column-major, ld k) = the upper trapezoid of A's first k
+// rows (A column-major, ld lda), conjugated if conj_r; zero below the diagonal.
+template <typename T>
+__global__ void k_qr_r_extract(const cx<T> *__restrict__ A, int lda, int k, int ncols, int conj_r,
+                               cx<T> *__restrict__ out) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)k * ncols) return;
+    const int j = (int)(e / k), i = (int)(e % k);
+    cx<T> v = zero_cx<T>();
+    if (i <= j) {
+        v = A[(size_t)j * lda + i];
+        if (conj_r) v = conj(v);
+    }
+    out[e] = v;
+}
+
+// C (m x k, column-major) = [I_k; 0].
+template <typename T>
+__global__ void k_qr_eye(int m, int k, cx<T> *__restrict__ C) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)m * k) return;
+    const int j = (int)(e / m), i = (int)(e % m);
+    C[e] = mk<T>(i == j ? T(1) : T(0), T(0));
+}
+
+template <typename T>
+void launch_qr_r_extract(const void *A, int lda, int k, int ncols, int conj_r, void *out,
+                         hipStream_t s) {
+    const size_t tot = (size_t)k * ncols;
+    if (tot)
+        k_qr_r_extract<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>((const cx<T> *)A, lda, k,
+                                                                        ncols, conj_r, (cx<T> *)out);
+}
+template <typename T>
+void launch_qr_eye(int m, int k, void *C, hipStream_t s) {
+    const size_t tot = (size_t)m * k;
+    if (tot) k_qr_eye<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m, k, (cx<T> *)C);
+}
+template void launch_qr_r_extract<float>(const void *, int, int, int, int, void *, hipStream_t);
+template void launch_qr_r_extract<double>(const void *, int, int, int, int, void *, hipStream_t);
+template void launch_qr_eye<float>(int, int, void *, hipStream_t);
+template void launch_qr_eye<double>(int, int, void *, hipStream_t);

@@ -242,6 +242,30 @@ def test_qr_preconditioned_circuit(prec):
         assert abs(F1 - F0) < 1e-5
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_qr_centre_moves_vs_oracle(prec):
+    """Centre moves by Householder QR (the oracle's own move): kept ranks,
+    bond dimensions and amplitudes against the oracle on a 14-qubit
+    truncating circuit."""
+    _say("case: qr moves", prec)
+    prog = C.brickwork_program(14, 12, 11)
+    o = oracle_run(prog, 0.97)
+    with P.EAState(prog.n_sites, "pure", prec) as st:
+        st.set_option(P.EA_OPT_SMALL_LAYERS, 0)
+        st.set_option(P.EA_OPT_QR_MOVES, 1)
+        st.profile(1)
+        st.run(prog, 0.97)
+        qr_launches = st.profile_read(P.EA_K_QR)["launches"]
+        psi, glog, bonds = st.statevector(), st.gate_log(), st.bond_dims()
+    assert qr_launches > 0
+    tol_w = 1e-12 if prec == "c128" else 1e-6
+    for g, r in zip(glog, o.log):
+        if protected(r, r.f_t, tol_w):
+            assert g["k"] == r.k
+    assert bonds == o.bond_dims()
+    np.testing.assert_allclose(psi, o.to_statevector(), atol=1e-10 if prec == "c128" else 2e-4)
+
+
 def test_ghz_chain_gpu():
     _say("case: ghz")
     n = 10
