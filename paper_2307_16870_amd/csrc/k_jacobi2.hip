@@ -75,16 +75,20 @@ constexpr int JRS = 64;  // rows staged in LDS per step
 // All loads of a thread are issued before the first LDS write, so their
 // latencies overlap instead of adding up.
 template <typename T, int NC>
-__device__ __forceinline__ void stage_rows(const cx<T> *__restrict__ X, int M, const int *cols,
-                                           int nc, int r0, int r_end, T (*Sr)[NC + 1],
-                                           T (*Si)[NC + 1], int tid) {
+__device__ __forceinline__ void stage_load(const cx<T> *__restrict__ X, int M, const int *cols,
+                                           int nc, int r0, int r_end, cx<T> (&v)[JRS * NC / 256],
+                                           int tid) {
     constexpr int PER = JRS * NC / 256;
-    cx<T> v[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int e = tid + 256 * i, c = e / JRS, row = r0 + e % JRS;
         v[i] = (c < nc && row < r_end) ? X[(size_t)cols[c] * M + row] : zero_cx<T>();
     }
+}
+template <typename T, int NC>
+__device__ __forceinline__ void stage_store(const cx<T> (&v)[JRS * NC / 256], T (*Sr)[NC + 1],
+                                            T (*Si)[NC + 1], int tid) {
+    constexpr int PER = JRS * NC / 256;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int e = tid + 256 * i, c = e / JRS, rr = e % JRS;
@@ -128,9 +132,13 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
         im[u] = MF::zero();
     }
     __syncthreads();
+    // rows of the next step are loaded while this step's products run
+    cx<T> v[JRS * NC / 256];
+    if (r_begin < r_end) stage_load<T, NC>(W, m, cols, nc, r_begin, r_end, v, tid);
     for (int r0 = r_begin; r0 < r_end; r0 += JRS) {
-        stage_rows<T, NC>(W, m, cols, nc, r0, r_end, Sr, Si, tid);
+        stage_store<T, NC>(v, Sr, Si, tid);
         __syncthreads();
+        if (r0 + JRS < r_end) stage_load<T, NC>(W, m, cols, nc, r0 + JRS, r_end, v, tid);
 #pragma unroll
         for (int u = 0; u < UPW; ++u) {
             if (ti_[u] < 0) continue;
@@ -408,10 +416,14 @@ __global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx
             Ji[e / NC][e % NC] = v[i].y;
         }
     }
+    // rows of the next step are loaded while this step's products run
+    cx<T> sv[JRS * NC / 256];
+    stage_load<T, NC>(X, M, cols, nc, r_begin, r_end, sv, tid);
     for (int r0 = r_begin; r0 < r_end; r0 += JRS) {
         __syncthreads();
-        stage_rows<T, NC>(X, M, cols, nc, r0, r_end, Sr, Si, tid);
+        stage_store<T, NC>(sv, Sr, Si, tid);
         __syncthreads();
+        if (r0 + JRS < r_end) stage_load<T, NC>(X, M, cols, nc, r0 + JRS, r_end, sv, tid);
         typename MF::acc re[TPW], im[TPW];
 #pragma unroll
         for (int u = 0; u < TPW; ++u) {
