@@ -416,6 +416,7 @@ __global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx
             Ji[e / NC][e % NC] = v[i].y;
         }
     }
+    __syncthreads();  // cols[] is written by other waves in pair_columns
     // rows of the next step are loaded while this step's products run
     cx<T> sv[JRS * NC / 256];
     stage_load<T, NC>(X, M, cols, nc, r_begin, r_end, sv, tid);
