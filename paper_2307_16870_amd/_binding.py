@@ -202,7 +202,10 @@ def mps_apply_2q(h, site, op, fidelity_budget=-1.0):
 def mps_apply_layer(h, sites, ops, budgets=None):
     """Returns (status, achieved f per gate in the order given)."""
     s = np.ascontiguousarray(np.asarray(sites, dtype=np.int32))
-    o = _c(np.stack([np.asarray(x) for x in ops]) if isinstance(ops, (list, tuple)) else ops)
+    if len(s) == 0:  # an empty layer: nothing to pass
+        o = _c(np.zeros((1, 4, 4)))
+    else:
+        o = _c(np.stack([np.asarray(x) for x in ops]) if isinstance(ops, (list, tuple)) else ops)
     b = None if budgets is None else np.ascontiguousarray(np.asarray(budgets, dtype=np.float64))
     f = np.zeros(len(s))
     rc = _chk(_lib.mps_apply_layer(h, len(s), _ip(s), _dp(o), _dp(b) if b is not None else None,

@@ -383,6 +383,12 @@ int svd_core(ea_mps *h, int m, int n) {
             break;
         }
     }
+    if (sizeof(T) == 4 && h->reorth) {
+        // FP32 right vectors carry a norm drift that grows with the rotations
+        // applied to them; unit columns keep U S V^H (and the norm) exact.
+        ProfScope ps(h, EA_K_NORMS, 4.0 * n * (double)n, c * (2.0 * m + 3.0 * n) * (double)n);
+        launch_unit_right<T>(h->W.p, m, h->V.p, n, h->stream);
+    }
     launch_fill_int(sweeps_dev, 1, sweeps, h->stream);
     launch_fill_int(sweeps_dev + 1, 1, conv, h->stream);
     return EA_OK;
@@ -574,47 +580,84 @@ void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int 
 }
 
 // FP64 re-orthogonalisation of the isometric factor written by an FP32
-// factorisation (one Loewdin step).  cols = 1: X (rows x k, row-major) should
+// factorisation (Loewdin steps).  cols = 1: X (rows x k, row-major) should
 // have orthonormal columns and the neighbour N (k x ncols) absorbs R from the
 // left; cols = 0: X (k x rows) should have orthonormal rows and N (nrows x k)
 // absorbs R from the right.  With G = X^H X (or X X^H) = I + E formed in FP64,
-// X <- X (I - E/2) and N <- (I + E/2) N keep the product to O(E^2).
+// X <- X (I - E/2) and N <- (I + E/2) N leave X^H X - I = -(3/4) E^2 + O(E^3)
+// and change the product by the factor I - E^2/4; the entries of E^2 are at
+// most r, the largest squared row norm of E.  Two corrections hold both to
+// 1e-6: once r/4 exceeds it, N also takes C = I + E^2/4 (product factor
+// I - E^4/16; the loss E^2/4 falls on the heavy columns, whose rows of E
+// collect the errors of the many light columns, and would bias the kept
+// weights); while 3r/4 exceeds it, a further step runs (three at most).
+// Well-conditioned factors need neither; wide ill-conditioned ones (thousands
+// of kept columns over several decades of singular values) take both once.
 template <typename T>
 int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) {
     if (sizeof(T) == 8 || !h->reorth || k < 1) return EA_OK;
     const size_t nx = (size_t)rows * k;
-    TRY(ensure(h, h->ro_x64, 16 * nx));
-    TRY(ensure(h, h->ro_g, 16 * (size_t)k * k));
+    TRY(ensure(h, h->ro_x64, 16 * std::max(nx, (size_t)k * k)));
+    TRY(ensure(h, h->ro_g, 16 * (size_t)k * k + 256));
     TRY(ensure(h, h->ro_y, h->csz * (size_t)k * k));
     TRY(ensure(h, h->ro_r, h->csz * (size_t)k * k));
     TRY(ensure(h, h->ro_t, h->csz * std::max(nx, (size_t)k * nother)));
-    ProfScope ps(h, EA_K_OTHER, 8.0 * rows * (double)k * k * 2 + 8.0 * k * (double)k * nother,
-                 (double)h->csz * (3.0 * nx + 2.0 * k * (double)nother));
-    launch_to_c128<T>(X, (double *)h->ro_x64.p, nx, h->stream);
-    if (cols)
-        launch_gemm_ex<double>(1, 0, k, k, rows, 1, 0, h->ro_x64.p, k, h->ro_x64.p, k, 0, 0,
-                               h->ro_g.p, k, h->stream);
-    else
-        launch_gemm_ex<double>(0, 1, k, k, rows, 1, 0, h->ro_x64.p, rows, h->ro_x64.p, rows, 0, 0,
-                               h->ro_g.p, k, h->stream);
-    launch_reorth_factors<T>(k, h->ro_g.p, h->ro_y.p, h->ro_r.p, h->stream);
-    if (cols) {
-        launch_gemm_ex<T>(0, 0, rows, k, k, 1, 0, X, k, h->ro_y.p, k, 0, 0, h->ro_t.p, k, h->stream);
-        HIPCHK(h, hipMemcpyAsync(X, h->ro_t.p, h->csz * nx, hipMemcpyDeviceToDevice, h->stream));
-        launch_gemm_ex<T>(0, 0, k, nother, k, 1, 0, h->ro_r.p, k, N, nother, 0, 0, h->ro_t.p,
-                          nother, h->stream);
-        HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)k * nother,
-                                 hipMemcpyDeviceToDevice, h->stream));
-    } else {
-        launch_gemm_ex<T>(0, 0, k, rows, k, 1, 0, h->ro_y.p, k, X, rows, 0, 0, h->ro_t.p, rows,
-                          h->stream);
-        HIPCHK(h, hipMemcpyAsync(X, h->ro_t.p, h->csz * nx, hipMemcpyDeviceToDevice, h->stream));
-        launch_gemm_ex<T>(0, 0, nother, k, k, 1, 0, N, k, h->ro_r.p, k, 0, 0, h->ro_t.p, k,
-                          h->stream);
-        HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)nother * k,
-                                 hipMemcpyDeviceToDevice, h->stream));
+    void *rowsq = (char *)h->ro_g.p + 16 * (size_t)k * k;
+    // N <- F N (cols) or N F (rows) for a k x k factor F in T precision
+    auto absorb = [&](const void *F) -> int {
+        if (cols) {
+            launch_gemm_ex<T>(0, 0, k, nother, k, 1, 0, F, k, N, nother, 0, 0, h->ro_t.p, nother,
+                              h->stream);
+            HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)k * nother,
+                                     hipMemcpyDeviceToDevice, h->stream));
+        } else {
+            launch_gemm_ex<T>(0, 0, nother, k, k, 1, 0, N, k, F, k, 0, 0, h->ro_t.p, k,
+                              h->stream);
+            HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)nother * k,
+                                     hipMemcpyDeviceToDevice, h->stream));
+        }
+        return EA_OK;
+    };
+    for (int step = 0; step < 3; ++step) {
+        double r;
+        {
+            ProfScope ps(h, EA_K_OTHER, 8.0 * rows * (double)k * k * 2 + 8.0 * k * (double)k * nother,
+                         (double)h->csz * (3.0 * nx + 2.0 * k * (double)nother));
+            launch_to_c128<T>(X, (double *)h->ro_x64.p, nx, h->stream);
+            if (cols)
+                launch_gemm_ex<double>(1, 0, k, k, rows, 1, 0, h->ro_x64.p, k, h->ro_x64.p, k, 0,
+                                       0, h->ro_g.p, k, h->stream);
+            else
+                launch_gemm_ex<double>(0, 1, k, k, rows, 1, 0, h->ro_x64.p, rows, h->ro_x64.p,
+                                       rows, 0, 0, h->ro_g.p, k, h->stream);
+            HIPCHK(h, hipMemsetAsync(rowsq, 0, sizeof(double), h->stream));
+            launch_reorth_factors<T>(k, h->ro_g.p, h->ro_y.p, h->ro_r.p, rowsq, h->stream);
+            HIPCHK(h, hipMemcpyAsync(h->dbl_host, rowsq, sizeof(double), hipMemcpyDeviceToHost,
+                                     h->stream));
+            if (cols)
+                launch_gemm_ex<T>(0, 0, rows, k, k, 1, 0, X, k, h->ro_y.p, k, 0, 0, h->ro_t.p, k,
+                                  h->stream);
+            else
+                launch_gemm_ex<T>(0, 0, k, rows, k, 1, 0, h->ro_y.p, k, X, rows, 0, 0, h->ro_t.p,
+                                  rows, h->stream);
+            HIPCHK(h, hipMemcpyAsync(X, h->ro_t.p, h->csz * nx, hipMemcpyDeviceToDevice,
+                                     h->stream));
+            TRY(absorb(h->ro_r.p));
+            LAUNCHCHK(h);
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            r = h->dbl_host[0];
+        }
+        if (0.25 * r > 1e-6) {
+            ProfScope ps(h, EA_K_OTHER, 8.0 * k * (double)k * k + 8.0 * k * (double)k * nother,
+                         16.0 * 3.0 * k * (double)k + (double)h->csz * 2.0 * k * (double)nother);
+            launch_gemm_ex<double>(0, 0, k, k, k, 1, 0, h->ro_g.p, k, h->ro_g.p, k, 0, 0,
+                                   h->ro_x64.p, k, h->stream);
+            launch_reorth_corr<T>(k, h->ro_x64.p, h->ro_g.p, h->ro_r.p, h->stream);
+            TRY(absorb(h->ro_r.p));
+            LAUNCHCHK(h);
+        }
+        if (0.75 * r <= 1e-6) break;
     }
-    LAUNCHCHK(h);
     return EA_OK;
 }
 

@@ -64,6 +64,9 @@ void launch_to_colmajor(const void *in, void *out, int M, int N, int conj_copy, 
 // s_out[j] = || column j || (FP64 accumulation), column-major m x n.
 template <typename T>
 void launch_colnorms(const void *W, int m, int n, double *s_out, hipStream_t s);
+// Divides column j of V (n x n) and W (m x n), column-major, by |V_j| (FP64).
+template <typename T>
+void launch_unit_right(void *W, int m, void *V, int n, hipStream_t s);
 // Write-back gather: for j < k, alpha_j = s_j^es * scale^ec;
 //   rows_out:  out[j*X + x] = alpha_j * op(src[perm[j]*ld + x])
 //   transposed: out[x*k + j] = alpha_j * op(src[perm[j]*ld + x])
@@ -205,9 +208,16 @@ void launch_svdvjp_P(int r, const void *J, const void *K, const double *s, const
 template <typename T>
 void launch_gbar_grad(const void *Ab, const void *A, int chiL, int chiR, double *partial,
                       const double *dg, double *grad, int param, hipStream_t s);
-// Y = I - E/2, R = I + E/2 from G = I + E (k x k, complex FP64).
+// Y = I - E/2, R = I + E/2 from G = I + E (k x k, complex FP64); raises the
+// double at rowsq_max (device, non-negative, cleared by the caller) to the
+// largest squared row norm of E.
 template <typename T>
-void launch_reorth_factors(int k, const void *G, void *Y, void *R, hipStream_t s);
+void launch_reorth_factors(int k, const void *G, void *Y, void *R, void *rowsq_max,
+                           hipStream_t s);
+// C = (G2 - 2 G + 5 I) / 4 = I + E^2/4 from G = I + E and G2 = G G (k x k,
+// complex FP64).
+template <typename T>
+void launch_reorth_corr(int k, const void *G2, const void *G, void *C, hipStream_t s);
 
 // ---- device-resident small-bond layers (k_small.hip) ----
 constexpr int SM_N = 128;      // columns of a factorisation (bonds <= SM_N / d)

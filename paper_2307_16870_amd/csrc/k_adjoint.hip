@@ -304,24 +304,62 @@ void launch_gbar_grad(const void *Ab, const void *A, int chiL, int chiR, double 
 // From the Gram matrix G = X^H X = I + E of a nearly orthonormal factor (FP64):
 // Y = I - E/2 (the Loewdin correction X <- X Y) and R = I + E/2 (absorbed by
 // the neighbour, so that X Y R = X + O(E^2)), both stored in T.
+// One workgroup per row i of G = I + E: writes row i of Y = I - E/2 and
+// R = I + E/2 and raises *rowsq_max to sum_j |E_ij|^2 if larger (the bit
+// pattern of a non-negative double orders like the unsigned integer).
 template <typename T>
-__global__ void k_reorth_factors(int k, const cx<double> *__restrict__ G, cx<T> *__restrict__ Y,
-                                 cx<T> *__restrict__ R) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= k * k) return;
-    const int i = idx / k, j = idx % k;
-    const double ex = G[idx].x - (i == j ? 1.0 : 0.0), ey = G[idx].y;
-    Y[idx] = mk<T>((T)((i == j ? 1.0 : 0.0) - 0.5 * ex), (T)(-0.5 * ey));
-    R[idx] = mk<T>((T)((i == j ? 1.0 : 0.0) + 0.5 * ex), (T)(0.5 * ey));
+__global__ __launch_bounds__(256) void k_reorth_factors(int k, const cx<double> *__restrict__ G,
+                                                        cx<T> *__restrict__ Y,
+                                                        cx<T> *__restrict__ R,
+                                                        unsigned long long *rowsq_max) {
+    __shared__ double part[4];
+    const int i = blockIdx.x;
+    const size_t row = (size_t)i * k;
+    double sq = 0.0;
+    for (int j = threadIdx.x; j < k; j += 256) {
+        const double ex = G[row + j].x - (i == j ? 1.0 : 0.0), ey = G[row + j].y;
+        sq += ex * ex + ey * ey;
+        Y[row + j] = mk<T>((T)((i == j ? 1.0 : 0.0) - 0.5 * ex), (T)(-0.5 * ey));
+        R[row + j] = mk<T>((T)((i == j ? 1.0 : 0.0) + 0.5 * ex), (T)(0.5 * ey));
+    }
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = part[0] + part[1] + part[2] + part[3];
+        atomicMax(rowsq_max, (unsigned long long)__double_as_longlong(t));
+    }
 }
 template <typename T>
-void launch_reorth_factors(int k, const void *G, void *Y, void *R, hipStream_t s) {
-    const int n = k * k;
-    k_reorth_factors<T><<<(n + 255) / 256, 256, 0, s>>>(k, (const cx<double> *)G, (cx<T> *)Y,
-                                                        (cx<T> *)R);
+void launch_reorth_factors(int k, const void *G, void *Y, void *R, void *rowsq_max,
+                           hipStream_t s) {
+    k_reorth_factors<T><<<k, 256, 0, s>>>(k, (const cx<double> *)G, (cx<T> *)Y, (cx<T> *)R,
+                                          (unsigned long long *)rowsq_max);
 }
-template void launch_reorth_factors<float>(int, const void *, void *, void *, hipStream_t);
-template void launch_reorth_factors<double>(int, const void *, void *, void *, hipStream_t);
+// Absorb correction C = I + E^2/4 = (G^2 - 2 G + 5 I) / 4 from G = I + E and
+// G2 = G G (both FP64): after R = I + E/2 and Y = I - E/2, applying C as
+// well gives Y R C = I - E^4/16 in place of Y R = I - E^2/4.
+template <typename T>
+__global__ void k_reorth_corr(int k, const cx<double> *__restrict__ G2,
+                              const cx<double> *__restrict__ G, cx<T> *__restrict__ C) {
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)k * k) return;
+    const bool diag = idx / k == idx % k;
+    C[idx] = mk<T>((T)(0.25 * (G2[idx].x - 2.0 * G[idx].x + (diag ? 5.0 : 0.0))),
+                   (T)(0.25 * (G2[idx].y - 2.0 * G[idx].y)));
+}
+template <typename T>
+void launch_reorth_corr(int k, const void *G2, const void *G, void *C, hipStream_t s) {
+    const size_t n = (size_t)k * k;
+    k_reorth_corr<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+        k, (const cx<double> *)G2, (const cx<double> *)G, (cx<T> *)C);
+}
+template void launch_reorth_corr<float>(int, const void *, const void *, void *, hipStream_t);
+template void launch_reorth_corr<double>(int, const void *, const void *, void *, hipStream_t);
+template void launch_reorth_factors<float>(int, const void *, void *, void *, void *,
+                                           hipStream_t);
+template void launch_reorth_factors<double>(int, const void *, void *, void *, void *,
+                                            hipStream_t);
 
 #define INST(T)                                                                                  \
     template void launch_gemm_ex<T>(int, int, int, int, int, double, double, const void *, int,  \

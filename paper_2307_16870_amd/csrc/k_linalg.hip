@@ -265,6 +265,46 @@ void launch_colnorms(const void *W, int m, int n, double *s_out, hipStream_t s) 
     k_colnorms<T><<<n, 256, 0, s>>>((const cx<T> *)W, m, s_out);
 }
 
+// Unit right vectors: one workgroup per column j divides column j of V
+// (n x n) and of W = A V (m x n), both column-major, by the FP64 norm of
+// V's column j.  W = A V still holds, V's columns have unit norm to the
+// storage precision and W's column norms become the singular values; a
+// low-precision rotation sequence otherwise leaves a norm drift in V that
+// grows with the number of rotations applied.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unit_right(cx<T> *__restrict__ W, int m,
+                                                    cx<T> *__restrict__ V, int n) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    cx<T> *v = V + (size_t)j * n, *w = W + (size_t)j * m;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const cx<T> a = v[i];
+        acc += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (!(red[0] > 0.0)) return;
+    const double inv = 1.0 / sqrt(red[0]);
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const cx<T> a = v[i];
+        v[i] = mk<T>((T)(inv * (double)a.x), (T)(inv * (double)a.y));
+    }
+    for (int i = threadIdx.x; i < m; i += 256) {
+        const cx<T> a = w[i];
+        w[i] = mk<T>((T)(inv * (double)a.x), (T)(inv * (double)a.y));
+    }
+}
+
+template <typename T>
+void launch_unit_right(void *W, int m, void *V, int n, hipStream_t s) {
+    k_unit_right<T><<<n, 256, 0, s>>>((cx<T> *)W, m, (cx<T> *)V, n);
+}
+
 // ---------------------------------------------------------------------------
 // Sort (descending, ties by index), suffix sums of s^2 and the kept-rank
 // search of Sec. VI in one workgroup.
@@ -510,6 +550,7 @@ void launch_fill_int(int *p, int n, int v, hipStream_t s) {
     template void launch_eye<T>(void *, int, hipStream_t);                                    \
     template void launch_to_colmajor<T>(const void *, void *, int, int, int, hipStream_t);    \
     template void launch_colnorms<T>(const void *, int, int, double *, hipStream_t);          \
+    template void launch_unit_right<T>(void *, int, void *, int, hipStream_t);                \
     template void launch_gather<T>(const void *, int, const int *, const double *,            \
                                    const ea_dev_rec *, int, int, int, int, int, int, void *,  \
                                    hipStream_t);                                              \

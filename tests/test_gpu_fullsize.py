@@ -100,6 +100,40 @@ def test_full_size_mpo_update(prec):
     _check_update(prec, *_single(prec, 4, 512, f_t, seed=3030), f_t)
 
 
+def test_full_size_mpo_update_chi1024_cross_precision():
+    """The largest factorisation the workloads reach: one MPO update at
+    chi = 1024, d = 4 (Theta 4096 x 4096).  The CPU oracle cannot take this
+    SVD within a test, so the FP64 GPU path (pinned to the oracle up to
+    2048 x 2048) is the reference for FP32: kept rank, f and total weight.
+    Both: the new left site is an isometry, and f T equals the weight of the
+    kept spectrum carried by the centre site (its row norms)."""
+    print("case: full-size MPO update chi=1024 (Theta 4096 x 4096)", flush=True)
+    chi, d, f_t = 1024, 4, 1 - 8.77e-4
+    tens = C.random_mps_tensors([1, chi, chi, chi, 1], d, seed=4096)
+    u = C.haar_unitary(np.random.default_rng(4096))
+    G = C.depolarizing2_superop(1e-3) @ C.unitary_superop(u)
+    out = {}
+    for prec in ("c128", "c64"):
+        with P.EAState(4, "mixed", prec) as st:
+            st.load(tens, 1)
+            rc, f = st.apply_2q(1, G, f_t)
+            g = st.gate_log()[0]
+            a1, a2 = st.site(1), st.site(2)
+        k = g["k"]
+        A = a1.reshape(-1, k).astype(np.complex128)  # measured in FP64
+        iso = np.abs(A.conj().T @ A - np.eye(k)).max()
+        s_kept = np.linalg.norm(a2.reshape(k, -1), axis=1)  # diag(s) V^H / sigma
+        print(prec, "k", k, "f", f, "sweeps", g["sweeps"], "isometry", iso, flush=True)
+        assert iso < (1e-12 if prec == "c128" else 1e-6)
+        assert abs(np.sum(s_kept ** 2) - 1.0) < (1e-10 if prec == "c128" else 1e-5)
+        assert f >= f_t - (1e-12 if prec == "c128" else 1e-5) or g["capped"]
+        out[prec] = (k, f, g["total"])
+    (k64, f64, T64), (k32, f32, T32) = out["c128"], out["c64"]
+    assert abs(k32 - k64) <= max(2, k64 // 500)
+    assert abs(f32 - f64) < 1e-5
+    assert abs(T32 - T64) < 1e-4 * T64
+
+
 def test_full_circuit_bench_config_invariants():
     """50 qubits, depth 20, F_min 0.99, chi <= 1024, mixed precision."""
     print("case: full circuit invariants", flush=True)
@@ -112,7 +146,7 @@ def test_full_circuit_bench_config_invariants():
         center = st.center()
         worst = 0.0
         for i in range(prog.n_sites):
-            a = st.site(i)
+            a = st.site(i).astype(np.complex128)  # measured in FP64
             cl, d, cr = a.shape
             if i < center:
                 m = a.reshape(cl * d, cr)

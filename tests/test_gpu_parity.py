@@ -383,3 +383,35 @@ def test_cap_flags_warning():
         assert any(r["capped"] for r in st.gate_log())
     o = oracle_run(prog, 0.99, chi_max=2)
     assert abs(F - o.fidelity_estimate()[0]) < 1e-10
+
+
+@pytest.mark.parametrize("small", [0, 64])
+def test_empty_layer_is_a_no_op(small):
+    _say("case: empty layer", small)
+    prog = C.brickwork_program(8, 4, 17)
+    with P.EAState(8, "pure", "c128") as st:
+        st.set_option(P.EA_OPT_SMALL_LAYERS, small)
+        st.run(prog, 0.99)
+        psi, log, bonds = st.statevector(), st.gate_log(), st.bond_dims()
+        rc, f = st.apply_layer([], [])
+        assert rc == P.EA_OK and f.size == 0
+        assert st.gate_log() == log and st.bond_dims() == bonds
+        np.testing.assert_array_equal(st.statevector(), psi)
+
+
+def test_zero_operator_is_rejected_and_state_kept():
+    """An operator that annihilates the state (Theta = 0) is an error; the
+    state is left as it was (the centre may have moved, which does not
+    change it)."""
+    _say("case: zero operator")
+    prog = C.brickwork_program(8, 4, 18)
+    with P.EAState(8, "pure", "c128") as st:
+        st.set_option(P.EA_OPT_SMALL_LAYERS, 0)
+        st.run(prog, 0.99)
+        psi, n_log = st.statevector(), len(st.gate_log())
+        with pytest.raises(P.EAError) as e:
+            st.apply_2q(4, np.zeros((4, 4), complex))
+        assert e.value.code == P.EA_EINVAL
+        assert len(st.gate_log()) == n_log
+        np.testing.assert_allclose(st.statevector(), psi, atol=1e-12)
+
