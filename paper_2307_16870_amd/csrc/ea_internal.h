@@ -596,6 +596,7 @@ void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int 
 template <typename T>
 int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) {
     if (sizeof(T) == 8 || !h->reorth || k < 1) return EA_OK;
+    TRY(blas_ready(h));
     const size_t nx = (size_t)rows * k;
     TRY(ensure(h, h->ro_x64, 16 * std::max(nx, (size_t)k * k)));
     TRY(ensure(h, h->ro_g, 16 * (size_t)k * k + 256));
@@ -603,19 +604,17 @@ int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) 
     TRY(ensure(h, h->ro_r, h->csz * (size_t)k * k));
     TRY(ensure(h, h->ro_t, h->csz * std::max(nx, (size_t)k * nother)));
     void *rowsq = (char *)h->ro_g.p + 16 * (size_t)k * k;
+    // Row-major products through column-major GEMMs: the row-major C = A B
+    // (m x n) is the column-major C^T = B^T A^T.
     // N <- F N (cols) or N F (rows) for a k x k factor F in T precision
     auto absorb = [&](const void *F) -> int {
-        if (cols) {
-            launch_gemm_ex<T>(0, 0, k, nother, k, 1, 0, F, k, N, nother, 0, 0, h->ro_t.p, nother,
-                              h->stream);
-            HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)k * nother,
-                                     hipMemcpyDeviceToDevice, h->stream));
-        } else {
-            launch_gemm_ex<T>(0, 0, nother, k, k, 1, 0, N, k, F, k, 0, 0, h->ro_t.p, k,
-                              h->stream);
-            HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)nother * k,
-                                     hipMemcpyDeviceToDevice, h->stream));
-        }
+        if (cols)
+            TRY(blas_gemm<T>(h, 'N', 'N', nother, k, k, 1.0, N, nother, F, k, 0.0, h->ro_t.p,
+                             nother));
+        else
+            TRY(blas_gemm<T>(h, 'N', 'N', k, nother, k, 1.0, F, k, N, k, 0.0, h->ro_t.p, k));
+        HIPCHK(h, hipMemcpyAsync(N, h->ro_t.p, h->csz * (size_t)k * nother,
+                                 hipMemcpyDeviceToDevice, h->stream));
         return EA_OK;
     };
     for (int step = 0; step < 3; ++step) {
@@ -624,22 +623,24 @@ int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) 
             ProfScope ps(h, EA_K_OTHER, 8.0 * rows * (double)k * k * 2 + 8.0 * k * (double)k * nother,
                          (double)h->csz * (3.0 * nx + 2.0 * k * (double)nother));
             launch_to_c128<T>(X, (double *)h->ro_x64.p, nx, h->stream);
+            // G = X^H X (cols) or X X^H (rows), row-major k x k, in FP64
             if (cols)
-                launch_gemm_ex<double>(1, 0, k, k, rows, 1, 0, h->ro_x64.p, k, h->ro_x64.p, k, 0,
-                                       0, h->ro_g.p, k, h->stream);
+                TRY(blas_gemm<double>(h, 'N', 'C', k, k, rows, 1.0, h->ro_x64.p, k, h->ro_x64.p,
+                                      k, 0.0, h->ro_g.p, k));
             else
-                launch_gemm_ex<double>(0, 1, k, k, rows, 1, 0, h->ro_x64.p, rows, h->ro_x64.p,
-                                       rows, 0, 0, h->ro_g.p, k, h->stream);
+                TRY(blas_gemm<double>(h, 'C', 'N', k, k, rows, 1.0, h->ro_x64.p, rows,
+                                      h->ro_x64.p, rows, 0.0, h->ro_g.p, k));
             HIPCHK(h, hipMemsetAsync(rowsq, 0, sizeof(double), h->stream));
             launch_reorth_factors<T>(k, h->ro_g.p, h->ro_y.p, h->ro_r.p, rowsq, h->stream);
             HIPCHK(h, hipMemcpyAsync(h->dbl_host, rowsq, sizeof(double), hipMemcpyDeviceToHost,
                                      h->stream));
+            // X <- X Y (cols) or Y X (rows)
             if (cols)
-                launch_gemm_ex<T>(0, 0, rows, k, k, 1, 0, X, k, h->ro_y.p, k, 0, 0, h->ro_t.p, k,
-                                  h->stream);
+                TRY(blas_gemm<T>(h, 'N', 'N', k, rows, k, 1.0, h->ro_y.p, k, X, k, 0.0,
+                                 h->ro_t.p, k));
             else
-                launch_gemm_ex<T>(0, 0, k, rows, k, 1, 0, h->ro_y.p, k, X, rows, 0, 0, h->ro_t.p,
-                                  rows, h->stream);
+                TRY(blas_gemm<T>(h, 'N', 'N', rows, k, k, 1.0, X, rows, h->ro_y.p, k, 0.0,
+                                 h->ro_t.p, rows));
             HIPCHK(h, hipMemcpyAsync(X, h->ro_t.p, h->csz * nx, hipMemcpyDeviceToDevice,
                                      h->stream));
             TRY(absorb(h->ro_r.p));
@@ -650,8 +651,8 @@ int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) 
         if (0.25 * r > 1e-6) {
             ProfScope ps(h, EA_K_OTHER, 8.0 * k * (double)k * k + 8.0 * k * (double)k * nother,
                          16.0 * 3.0 * k * (double)k + (double)h->csz * 2.0 * k * (double)nother);
-            launch_gemm_ex<double>(0, 0, k, k, k, 1, 0, h->ro_g.p, k, h->ro_g.p, k, 0, 0,
-                                   h->ro_x64.p, k, h->stream);
+            TRY(blas_gemm<double>(h, 'N', 'N', k, k, k, 1.0, h->ro_g.p, k, h->ro_g.p, k, 0.0,
+                                  h->ro_x64.p, k));
             launch_reorth_corr<T>(k, h->ro_x64.p, h->ro_g.p, h->ro_r.p, h->stream);
             TRY(absorb(h->ro_r.p));
             LAUNCHCHK(h);
