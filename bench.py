@@ -420,9 +420,9 @@ def main():
     f64 = args.prec == "c128"
     mfma_peak = PEAKS["f64_mfma_TF"] if f64 else PEAKS["f32_mfma_TF"]
     alu_peak = PEAKS["f64_vector_TF"] if f64 else PEAKS["f32_vector_TF"]
-    bound_of = {"jacobi_gram": "mfma", "jacobi_apply": "mfma"}
+    bound_of = {"jacobi_gram": "mfma", "jacobi_apply": "mfma", "theta": "mfma"}
     kernel_of = {"jacobi_rot": "k_jeig", "jacobi_gram": "k_jgram", "jacobi_apply": "k_japply",
-                 "theta": "k_theta", "jacobi_fused": "k_jacobi_block"}
+                 "theta": "k_theta_mfma", "jacobi_fused": "k_jacobi_block"}
 
     def roof(name):
         fd = fams[name]
