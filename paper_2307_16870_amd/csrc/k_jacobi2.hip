@@ -106,6 +106,10 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
     constexpr int NT = NC / 16;
     constexpr int NU = NT * (NT + 1) / 2;  // upper-triangular 16x16 tiles
     constexpr int UPW = (NU + 3) / 4;       // tiles per wave
+    // NU = 4 UPW - 2 (NC = 64: 10 tiles): the last two tiles are shared by
+    // four waves, waves 0-1 taking the first half of every stage's rows and
+    // waves 2-3 the second, so that each wave issues 2.5 tiles' products
+    constexpr bool SPLIT = NU % 4 == 2;
     __shared__ T Sr[JRS][NC + 1], Si[JRS][NC + 1];
     __shared__ int cols[NC];
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
@@ -116,7 +120,8 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
     int ti_[UPW], tj_[UPW];
 #pragma unroll
     for (int u = 0; u < UPW; ++u) {
-        int t = wave + 4 * u, ti = 0, tj = 0, k = 0;
+        int t = (SPLIT && u == UPW - 1 && wave >= 2) ? 4 * u + wave - 2 : wave + 4 * u;
+        int ti = 0, tj = 0, k = 0;
         ti_[u] = -1;
         for (ti = 0; ti < NT; ++ti)
             for (tj = ti; tj < NT; ++tj, ++k)
@@ -143,8 +148,11 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
         for (int u = 0; u < UPW; ++u) {
             if (ti_[u] < 0) continue;
             const int pc = ti_[u] * 16 + lane % 16, qc = tj_[u] * 16 + lane % 16;
+            const bool half = SPLIT && u == UPW - 1;
+            const int kb = (half && wave >= 2) ? JRS / 2 : 0;
+            const int ke = (half && wave < 2) ? JRS / 2 : JRS;
 #pragma unroll 4
-            for (int k0 = 0; k0 < JRS; k0 += 4) {
+            for (int k0 = kb; k0 < ke; k0 += 4) {
                 const int kr = k0 + lane / 16;
                 const T ar = Sr[kr][pc], ai = Si[kr][pc];
                 const T br = Sr[kr][qc], bi = Si[kr][qc];
@@ -156,10 +164,31 @@ __global__ __launch_bounds__(256) void k_jgram(const cx<T> *__restrict__ W, int 
         }
         __syncthreads();
     }
+    if constexpr (SPLIT) {
+        // waves 2-3 hand their halves of the shared tiles to waves 0-1
+        // through LDS (free: the stage loop ended with a barrier)
+        T *hr = &Sr[0][0], *hi = &Si[0][0];
+        if (wave >= 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                hr[(wave - 2) * 256 + v * 64 + lane] = re[UPW - 1][v];
+                hi[(wave - 2) * 256 + v * 64 + lane] = im[UPW - 1][v];
+            }
+        }
+        __syncthreads();
+        if (wave < 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                re[UPW - 1][v] += hr[wave * 256 + v * 64 + lane];
+                im[UPW - 1][v] += hi[wave * 256 + v * 64 + lane];
+            }
+        }
+    }
     cx<T> *out = partial + ((size_t)pair * nchunks + chunk) * NC * NC;
 #pragma unroll
     for (int u = 0; u < UPW; ++u) {
         if (ti_[u] < 0) continue;
+        if (SPLIT && u == UPW - 1 && wave >= 2) continue;  // added into waves 0-1
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int p = ti_[u] * 16 + MF::row(lane, v), q = tj_[u] * 16 + lane % 16;

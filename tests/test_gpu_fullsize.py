@@ -134,6 +134,25 @@ def test_full_size_mpo_update_chi1024_cross_precision():
     assert abs(T32 - T64) < 1e-4 * T64
 
 
+def test_factorisation_above_the_size_limit_is_rejected():
+    """A two-site matrix of more than 4096 columns (d = 4, chi = 1025 on both
+    sides: Theta 4100 x 4100) is refused with EA_ETOOBIG before any kernel
+    runs; the state, its log and its bonds are unchanged."""
+    print("case: size limit (Theta 4100 x 4100)", flush=True)
+    chi, d = 1025, 4
+    tens = C.random_mps_tensors([1, chi, chi, chi, 1], d, seed=4100)
+    G = C.unitary_superop(C.haar_unitary(np.random.default_rng(4100)))
+    with P.EAState(4, "mixed", "c64") as st:
+        st.load(tens, 1)
+        before = [st.site(i) for i in range(4)]
+        with pytest.raises(P.EAError) as e:
+            st.apply_2q(1, G, 0.999)
+        assert e.value.code == P.EA_ETOOBIG
+        assert st.gate_log() == [] and st.bond_dims() == [chi, chi, chi]
+        for i in range(4):
+            np.testing.assert_array_equal(st.site(i), before[i])
+
+
 def test_full_circuit_bench_config_invariants():
     """50 qubits, depth 20, F_min 0.99, chi <= 1024, mixed precision."""
     print("case: full circuit invariants", flush=True)
