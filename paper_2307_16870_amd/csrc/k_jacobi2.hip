@@ -419,7 +419,6 @@ __global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx
     constexpr int NT = NC / 16;
     constexpr int TPW = (4 * NT) / 4;  // (JRS/16 row tiles x NT col tiles) / 4 waves
     __shared__ T Sr[JRS][NC + 1], Si[JRS][NC + 1];
-    __shared__ T Jr[NC][NC + 1], Ji[NC][NC + 1];
     __shared__ int cols[NC];
     const int pair = blockIdx.x;
     if (!rotflag[pair]) return;
@@ -432,17 +431,20 @@ __global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx
     const int r_begin = chunk * rpc, r_end = min(M, r_begin + rpc);
     if (r_begin >= r_end) return;
     const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, 256);
+    // Wave w's output tiles t = w + 4u all lie in column tile t % NT = w % NT
+    // (NT divides 4), so each lane's MFMA B operands, J[4i + lane/16][bq] for
+    // the NC/4 k-steps i, are the same for all its tiles: they are held in
+    // registers (no LDS copy of J).
+    static_assert(4 % NT == 0, "a wave's tiles share one column tile");
     const cx<T> *jin = Jin + (size_t)pair * NC * NC;
+    T jr[NC / 4], ji[NC / 4];
     {
-        constexpr int PER = NC * NC / 256;
-        cx<T> v[PER];
+        const int bq = (wave % NT) * 16 + lane % 16;
 #pragma unroll
-        for (int i = 0; i < PER; ++i) v[i] = jin[tid + 256 * i];
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            Jr[e / NC][e % NC] = v[i].x;
-            Ji[e / NC][e % NC] = v[i].y;
+        for (int i = 0; i < NC / 4; ++i) {
+            const cx<T> v = jin[(size_t)(4 * i + lane / 16) * NC + bq];
+            jr[i] = v.x;
+            ji[i] = v.y;
         }
     }
     __syncthreads();  // cols[] is written by other waves in pair_columns
@@ -459,18 +461,15 @@ __global__ __launch_bounds__(256) void k_japply(cx<T> *__restrict__ W, int m, cx
         for (int u = 0; u < TPW; ++u) {
             re[u] = MF::zero();
             im[u] = MF::zero();
-            const int t = wave + 4 * u;
-            const int ti = t / NT, tj = t % NT;
-            const int ar_row = ti * 16 + lane % 16, bq = tj * 16 + lane % 16;
-#pragma unroll 4
-            for (int k0 = 0; k0 < NC; k0 += 4) {
-                const int kc = k0 + lane / 16;
+            const int ar_row = ((wave + 4 * u) / NT) * 16 + lane % 16;
+#pragma unroll
+            for (int i = 0; i < NC / 4; ++i) {
+                const int kc = 4 * i + lane / 16;
                 const T ar = Sr[ar_row][kc], ai = Si[ar_row][kc];
-                const T br = Jr[kc][bq], bi = Ji[kc][bq];
-                re[u] = MF::op(ar, br, re[u]);
-                re[u] = MF::op(-ai, bi, re[u]);
-                im[u] = MF::op(ar, bi, im[u]);
-                im[u] = MF::op(ai, br, im[u]);
+                re[u] = MF::op(ar, jr[i], re[u]);
+                re[u] = MF::op(-ai, ji[i], re[u]);
+                im[u] = MF::op(ar, ji[i], im[u]);
+                im[u] = MF::op(ai, jr[i], im[u]);
             }
         }
         __syncthreads();
