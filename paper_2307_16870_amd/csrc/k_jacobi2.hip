@@ -307,6 +307,28 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         }
         return r;
     };
+    // Inter-block order: slot sl always rotates column sl of block a against
+    // column na + (sl + step) mod w of block b, so J's columns are held in
+    // registers: lane sl of a group of NP lanes keeps J[row][sl] (block a)
+    // and the block-b column it meets at the current step, and after each
+    // step takes the block-b values of slot (sl + 1) mod w.  After whole
+    // inner sweeps (w steps each) every block-b value is back at its slot.
+    constexpr int RGROUPS = NTH / NP;                 // row groups of NP lanes
+    constexpr int RI = (NC + RGROUPS - 1) / RGROUPS;  // rows per thread
+    constexpr bool REGJ = INTER != 0 && NP <= 64 && RGROUPS >= 1 && RI <= 4;
+    const int sl_j = tid % NP, grp_j = tid / NP;
+    cx<T> ja[RI], jb[RI];
+    int src_j = tid % 64;
+    if constexpr (REGJ) {
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const int row = grp_j + i * RGROUPS;
+            ja[i] = mk<T>(sl_j < na && row == sl_j ? T(1) : T(0), T(0));
+            jb[i] = mk<T>(sl_j < w && row == na + sl_j ? T(1) : T(0), T(0));
+        }
+        const int lane = tid % 64;
+        src_j = (lane & ~(NP - 1)) | (sl_j < w ? (sl_j + 1) % w : sl_j);
+    }
     int first = 0;
     if (nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
@@ -367,14 +389,24 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                 // while this step's rotations are applied to J (J <- J M)
                 if (step + 1 < nsteps && tid < npairs)
                     rec_[(step + 1) & 1][tid] = make_rot(tid, step + 1, slot);
-                for (int e = tid; e < NP * NC; e += NTH) {
-                    const int b = e / NC, row = e % NC;
-                    if (b >= npairs || row >= nc) continue;
-                    int p, q;
-                    slot_pq(b, step, p, q);
-                    const RotRec<T> rb = rec[b];
-                    const cx<T> jp = J[row][p], jq = J[row][q];
-                    if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
+                if constexpr (REGJ) {
+                    const RotRec<T> rb = rec[sl_j < npairs ? sl_j : 0];
+                    const bool on = sl_j < npairs && rb.on;
+#pragma unroll
+                    for (int i = 0; i < RI; ++i) {
+                        if (on) rot_pair(ja[i], rb.e * jb[i], rb.s, rb.gm, ja[i], jb[i]);
+                        jb[i] = mk<T>(__shfl(jb[i].x, src_j), __shfl(jb[i].y, src_j));
+                    }
+                } else {
+                    for (int e = tid; e < NP * NC; e += NTH) {
+                        const int b = e / NC, row = e % NC;
+                        if (b >= npairs || row >= nc) continue;
+                        int p, q;
+                        slot_pq(b, step, p, q);
+                        const RotRec<T> rb = rec[b];
+                        const cx<T> jp = J[row][p], jq = J[row][q];
+                        if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
+                    }
                 }
                 __syncthreads();
             }
@@ -384,6 +416,16 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
             __syncthreads();
             if (nr == 0) break;
         }
+    }
+    if constexpr (REGJ) {  // J from the registers (identity entries elsewhere)
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const int row = grp_j + i * RGROUPS;
+            if (row >= NC) continue;
+            if (sl_j < na) J[row][sl_j] = ja[i];
+            if (sl_j < w && na + sl_j < NC) J[row][na + sl_j] = jb[i];
+        }
+        __syncthreads();
     }
     cx<T> *jo = Jout + (size_t)pair * NC * NC;
     for (int e = tid; e < NC * NC; e += NTH) {
