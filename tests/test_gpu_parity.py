@@ -191,6 +191,35 @@ def test_tuning_table_launch_shape_vs_oracle(block, threads, wgs):
     np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("block,threads", [(20, 1024), (12, 128), (32, 256), (8, 64)])
+def test_rotation_kernel_shapes_vs_oracle(block, threads):
+    """Block widths below half the rotation kernel's tile (20 of 32 slots, 12
+    of 16: the block-b values of J cycle over w slots, not the tile's) and
+    thread counts that give each thread up to four J rows in registers (1024,
+    128) or too many, where J stays in LDS (256 at 64 columns, 64 at 32), set
+    through the options; every update meets the FP64 bar against the oracle."""
+    chis = (300, 260, 333)
+    _say("case: rotation kernel shape", block, threads)
+    tens = C.random_mps_tensors([1, *chis, 1], 2, seed=sum(chis))
+    G = C.haar_unitary(np.random.default_rng(5))
+    if chis not in _SINGLE_CACHE:
+        o = OracleMPS(4, "pure", keep_spectra=True)
+        o.load(tens, 1)
+        _SINGLE_CACHE[chis] = (o, o.apply_2q(1, G, 0.98))
+    o, rec = _SINGLE_CACHE[chis]
+    with P.EAState(4, "pure", "c128") as st:
+        st.set_option(P.EA_OPT_BLOCK, block)
+        st.set_option(P.EA_OPT_ROT_THREADS, threads)
+        st.load(tens, 1)
+        rc, f = st.apply_2q(1, G, 0.98)
+        g = st.gate_log()[0]
+        a1, a2 = st.site(1), st.site(2)
+    assert g["k"] == rec.k
+    assert abs(f - rec.f) < 1e-10
+    got, ref = gauge_free_pair(a1, a2), gauge_free_pair(o.A[1], o.A[2])
+    np.testing.assert_allclose(got, ref, atol=1e-10 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("chis", [(37, 70, 45), (160, 150, 129), (300, 260, 333)])
 def test_qr_preconditioned_update_vs_oracle(chis):
     """SVD through the Householder QR (Jacobi on R^H, left vectors Q V_x):
