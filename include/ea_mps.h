@@ -90,8 +90,12 @@ enum ea_option {
                                 1: one fused kernel per round (vector ALU) */
     EA_OPT_ROT_THREADS = 7,  /* threads of the per-pair rotation kernel: 64, 128, 256, 512,
                                 1024, or 0 (default: 16 per column of a block pair) */
-    EA_OPT_REORTH = 8,       /* FP32 precisions: 1 (default) re-orthogonalises every
-                                isometric factor in FP64 after its factorisation */
+    EA_OPT_REORTH = 8,       /* FP32 precisions: 1 (default) divides the right singular
+                                vectors of every factorisation by their FP64 norms (the
+                                rotations leave a norm drift) and re-orthogonalises every
+                                isometric factor in FP64 (Loewdin steps, the neighbour
+                                absorbing the inverse factor), holding X^H X - I and the
+                                change of the product within 1e-6; 0: neither */
     EA_OPT_JACOBI_ORDER = 9, /* three-kernel Jacobi: 1 (default) rotates the column pairs
                                 inside a block in the first round of a sweep only, later
                                 rounds rotate only pairs across the two blocks (every pair
