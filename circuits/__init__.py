@@ -31,9 +31,10 @@ import numpy as np
 
 __all__ = [
     "haar_unitary", "brickwork_pairs", "Program", "Op", "brickwork_program",
-    "unitary_superop", "depolarizing2_superop", "pauli_matrices",
+    "unitary_superop", "depolarizing1_superop", "depolarizing2_superop", "pauli_matrices",
     "ry", "rz", "CZ", "hea_angles", "hea_program", "hea_hamiltonian",
-    "random_mps_tensors", "config_program", "batched_programs",
+    "random_mps_tensors", "config_program", "batched_programs", "noisy_program",
+    "mirror_program",
 ]
 
 # ---------------------------------------------------------------------------
@@ -96,6 +97,20 @@ def unitary_superop(u: np.ndarray) -> np.ndarray:
     return k.reshape(16, 16)
 
 
+def depolarizing1_superop(p: float) -> np.ndarray:
+    """One-qubit depolarising channel in Pauli form, as a 4x4 superoperator.
+
+    rho -> (1-p) rho + p/3 * (X rho X + Y rho Y + Z rho Z), the one-qubit
+    counterpart of :func:`depolarizing2_superop` (the paper names the noise
+    parameters of one- and two-qubit gates without a formula).
+    """
+    paulis = pauli_matrices()
+    s = (1.0 - p) * np.eye(4, dtype=np.complex128)
+    for a in range(1, 4):
+        s = s + (p / 3.0) * unitary_superop(paulis[a])
+    return s
+
+
 def depolarizing2_superop(p: float) -> np.ndarray:
     """Two-qubit depolarising channel in Pauli form, as a 16x16 superoperator.
 
@@ -136,6 +151,9 @@ class Program:
     n_sites: int
     kind: str  # "pure" (d=2) or "mixed" (d=4)
     layers: List[List[Op]] = field(default_factory=list)
+    # noisy programs: the unitaries and noise strengths behind the fused
+    # operands, as (site, width, U, p) in program order
+    units: list = field(default_factory=list)
 
     @property
     def n_2q(self) -> int:
@@ -180,6 +198,51 @@ def brickwork_program(n_sites: int, depth: int, seed, kind: str = "pure",
                 m = u
             layer.append(Op(2, i, m, "haar"))
         prog.layers.append(layer)
+    return prog
+
+
+def noisy_program(n_sites: int, depth: int, seed, eps1: float, eps2: float) -> Program:
+    """Noisy mixed-state circuit with one- and two-qubit noise.
+
+    Each layer t first applies a Haar-random one-qubit unitary to every site,
+    each followed (fused, one 4x4 operand) by the one-qubit depolarising
+    channel of strength ``eps1``, then Haar-random two-qubit gates on the
+    brickwork pairs of sub-layer t, each followed (fused, one 16x16 operand) by
+    the two-qubit depolarising channel of strength ``eps2``.  Gates are drawn
+    in program order from ``numpy.random.default_rng(seed)``.  The unitaries
+    and strengths behind the fused operands are listed in ``Program.units``
+    as (site, width, U, p), for references that apply the channels directly.
+    """
+    rng = np.random.default_rng(seed)
+    prog = Program(n_sites=n_sites, kind="mixed")
+    dep1 = depolarizing1_superop(eps1)
+    dep2 = depolarizing2_superop(eps2)
+    units = []
+    for t in range(depth):
+        layer = []
+        for q in range(n_sites):
+            u = haar_unitary(rng, 2)
+            layer.append(Op(1, q, dep1 @ unitary_superop(u), "haar1+dep1"))
+            units.append((q, 1, u, eps1))
+        for i in brickwork_pairs(n_sites, t):
+            u = haar_unitary(rng, 4)
+            layer.append(Op(2, i, dep2 @ unitary_superop(u), "haar+dep2"))
+            units.append((i, 2, u, eps2))
+        prog.layers.append(layer)
+    prog.units = units
+    return prog
+
+
+def mirror_program(n_sites: int, depth: int, seed) -> Program:
+    """A brickwork Haar circuit of ``depth`` sub-layers followed by its
+    adjoint: the same layers in reverse order with every gate replaced by its
+    conjugate transpose, so the whole circuit is the identity."""
+    fwd = brickwork_program(n_sites, depth, seed)
+    prog = Program(n_sites=n_sites, kind="pure")
+    prog.layers = [list(layer) for layer in fwd.layers]
+    for layer in reversed(fwd.layers):
+        prog.layers.append([Op(2, op.site, op.mat.conj().T.copy(), "haar-adjoint")
+                            for op in layer])
     return prog
 
 

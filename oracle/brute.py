@@ -67,15 +67,36 @@ def apply_depolarizing2_rho(rho, n, i, p):
     return out
 
 
+def apply_depolarizing1_rho(rho, n, i, p):
+    """(1-p) rho + p/3 (X rho X + Y rho Y + Z rho Z) on qubit i."""
+    paulis = pauli_matrices()
+    out = (1.0 - p) * rho
+    for a in range(1, 4):
+        full = _full_op(n, i, 1, paulis[a])
+        out = out + (p / 3.0) * (full @ rho @ full.conj().T)
+    return out
+
+
+def apply_kraus_rho(rho, n, i, width, kraus):
+    """sum_K K rho K^dagger for Kraus operators on (i) or (i, i+1)."""
+    out = np.zeros_like(rho)
+    for k in kraus:
+        full = _full_op(n, i, width, k)
+        out = out + full @ rho @ full.conj().T
+    return out
+
+
 def run_density(n: int, gates) -> np.ndarray:
     """Exact final density matrix.  ``gates`` is a list of
-    (site, width, unitary, depolarising_p) applied in order to |0><0|^n."""
+    (site, width, unitary, depolarising_p) applied in order to |0><0|^n; the
+    depolarising channel of the gate's width follows each gate with p > 0."""
     rho = np.zeros((2 ** n, 2 ** n), dtype=np.complex128)
     rho[0, 0] = 1.0
     for site, width, u, p in gates:
         rho = apply_unitary_rho(rho, n, site, width, u)
         if p:
-            rho = apply_depolarizing2_rho(rho, n, site, p)
+            rho = apply_depolarizing2_rho(rho, n, site, p) if width == 2 else \
+                apply_depolarizing1_rho(rho, n, site, p)
     return rho
 
 

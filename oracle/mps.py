@@ -31,7 +31,9 @@ Readings of the paper taken here (each also listed in the design notes):
   least one value is always kept.
 * Targets: naive f_t = F_min^(1/n) (Eq. 14, n = number of two-qubit gates);
   global f_t = (F_min / P_g)^(1/(n - g)) before gate g; nearest
-  f_t = F_min^((g+1)/n) / P_g; all clamped to (0, 1].
+  f_t = F_min^((g+1)/n) / P_g; all clamped to (0, 1].  The fixed strategy
+  is the standard fixed-bond-dimension simulation the paper compares against
+  (Sec. VI, Fig. 4): every target is 1, so only the chi_max cap truncates.
 * A chi_max cap (end of Sec. VI) overrides the target; the achieved f is then
   recorded and the update is flagged as capped.
 * After truncation the kept values are renormalised to unit norm; for the MPO
@@ -47,7 +49,7 @@ import numpy as np
 
 from .jacobi import jacobi_svd
 
-NAIVE, GLOBAL, NEAREST = 0, 1, 2
+NAIVE, GLOBAL, NEAREST, FIXED = 0, 1, 2, 3
 
 
 @dataclass
@@ -111,6 +113,7 @@ class GateRecord:
     sweeps: int
     capped: bool
     s: Optional[np.ndarray] = None
+    lnS: float = 0.0  # MPO log-scale after this update (0 for pure states)
 
 
 class OracleMPS:
@@ -180,6 +183,8 @@ class OracleMPS:
             ft = 1.0 if left <= 0 else math.exp((math.log(self.f_min) - self.lnP) / left)
         elif self.strategy == NEAREST:
             ft = math.exp(math.log(self.f_min) * (g + 1) / n - self.lnP)
+        elif self.strategy == FIXED:
+            ft = 1.0
         else:
             raise ValueError(self.strategy)
         return min(1.0, max(ft, 1e-300))
@@ -270,7 +275,8 @@ class OracleMPS:
         capped = dec.capped if forced_k is None else False
         self.any_capped |= capped
         rec = GateRecord(self.g, i, chi_l, chi_m, chi_r, k, f_t, f, self.lnP,
-                         res.sweeps, capped, s.copy() if self.keep_spectra else None)
+                         res.sweeps, capped, s.copy() if self.keep_spectra else None,
+                         self.lnS)
         self.g += 1
         self.log.append(rec)
         return rec
