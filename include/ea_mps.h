@@ -76,7 +76,23 @@ enum ea_status {
     EA_ETOOBIG = -5     /* output buffer too small / N too large */
 };
 
-enum ea_strategy { EA_NAIVE = 0, EA_GLOBAL = 1, EA_NEAREST = 2 };
+/* Target schedules (Sec. VI).  EA_FIXED is the standard fixed-bond-dimension
+ * simulation the paper compares against (Sec. VI, Fig. 4): every target is 1,
+ * so only numerically zero values and the chi_max cap truncate. */
+enum ea_strategy { EA_NAIVE = 0, EA_GLOBAL = 1, EA_NEAREST = 2, EA_FIXED = 3 };
+
+/* Device-memory source of a handle.  alloc(ctx, bytes, stream) returns device
+ * memory usable by work enqueued on `stream` (a hipStream_t), or NULL;
+ * free(ctx, ptr, stream) releases it (the library has synchronised the
+ * stream first, or frees only memory that no pending work uses).  Both may be
+ * called from the thread that calls into the library, including the host
+ * workers of mps_apply_layer_batched.  Used, for example, to draw the state's
+ * memory from a framework's caching allocator.  Not part of the paper. */
+typedef struct ea_allocator {
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+    void *ctx;
+} ea_allocator;
 
 enum ea_option {
     EA_OPT_JACOBI_TOL = 0,   /* rotate a pair if |g| > tol*sqrt(a b); default m*eps */
@@ -199,22 +215,32 @@ typedef struct ea_gate_record {
     double f;        /* achieved truncation fidelity 1 - D(k)/T */
     double total;    /* T = sum of all s^2 */
     double lnP;      /* running log fidelity estimate after this update */
+    double lnS;      /* EA_MIXED: running log of the scale removed by renormalising the
+                        kept values (the unnormalised truncated state is exp(lnS) times
+                        the stored one); 0 for EA_PURE */
 } ea_gate_record;
 
-/* Create a product state (Sec. VI: simulations start from a product state).
- *  n_sites >= 1; kind: ea_kind; prec: ea_prec; chi_max: cap on the kept rank
+/* Create a product state (Sec. VI: simulations start from a product state;
+ * Sec. II, Eq. 2 with every bond dimension 1).
+ *  n_sites >= 2; kind: ea_kind; prec: ea_prec; chi_max: cap on the kept rank
  *  (0 = no cap, end of Sec. VI).
  *  local: NULL for |0...0> (pure) or |0><0|^N (mixed), else n_sites*d complex
  *  numbers, the d-vector of each site (vec(rho_i) for EA_MIXED).
+ *  alloc: NULL = hipMalloc / hipFree, else the source of all of the handle's
+ *  device memory (copied; its ctx must stay valid until mps_free).  Pinned
+ *  host staging buffers always come from hipHostMalloc.
  *  hip_stream: hipStream_t on which all work is enqueued; NULL = a private
  *  non-blocking stream created (default priority) and destroyed with the
  *  handle.
  *  out: receives the handle.  Returns EA_EINVAL on bad arguments, EA_ENOMEM if
  *  device memory cannot be allocated. */
 int mps_init_product(int n_sites, int kind, int prec, int chi_max,
-                     const double *local, void *hip_stream, ea_mps **out);
+                     const double *local, const ea_allocator *alloc, void *hip_stream,
+                     ea_mps **out);
 
-/* Release the handle and all its device memory.  NULL is ignored. */
+/* Release the handle and all its device memory (library bookkeeping, not
+ * part of the paper).  Synchronises the handle's stream first.  NULL is
+ * ignored. */
 void mps_free(ea_mps *h);
 
 /* Tuning and numerical options (ea_option).  EA_EINVAL on unknown option or
@@ -224,8 +250,9 @@ int mps_set_option(ea_mps *h, int option, double value);
 /* Target schedule (Sec. VI): F_min in (0, 1], n_2q_total >= 1 two-qubit gates
  * to come, strategy ea_strategy: naive f_t = F_min^(1/n) (Eq. 14); global
  * f_t = (F_min / P)^(1/(n - g)) before gate g; nearest f_t = F_min^((g+1)/n)
- * / P.  Targets are clamped to (0, 1].  Without a schedule every target is 1
- * (only numerically zero singular values are dropped). */
+ * / P; fixed f_t = 1 (only the cap truncates).  Targets are clamped to
+ * (0, 1].  Without a schedule every target is 1 (only numerically zero
+ * singular values are dropped). */
 int mps_set_schedule(ea_mps *h, double f_min, long n_2q_total, int strategy);
 
 /* One-site operator (Sec. II: one-qubit gates do not change bond dimensions).
@@ -242,7 +269,11 @@ int mps_apply_1q(ea_mps *h, int site, const double *op);
 int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget,
                  double *f_out);
 
-/* A layer of two-site updates on disjoint pairs (sites[j], sites[j]+1).
+/* A layer of two-site updates on disjoint pairs (sites[j], sites[j]+1): the
+ * update of Sec. V-VI applied to each gate of one circuit layer.  The paper
+ * applies gates one at a time with the canonical form kept (Sec. III, VI);
+ * the visiting order below is this library's choice (the centre walks the
+ * layer once, serpentine over a brickwork circuit).
  *  ops: n_gates consecutive d^2 x d^2 complex matrices.
  *  budgets: NULL (schedule) or n_gates targets, one per gate in the order
  *  given.  Gates are visited in increasing site order if the centre is
@@ -252,9 +283,23 @@ int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget,
 int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
                     const double *budgets, double *f_out);
 
-/* One layer on each of several independent states (batching: independent
- * circuits share nothing, Sec. VI).  State b applies n_gates[b] two-site
- * updates given, as for mps_apply_layer, by sites[b], ops[b] and budgets[b]
+/* Kept ranks forced (Sec. V-VI update with the truncation rule replaced):
+ * as mps_apply_layer with the schedule's targets, except that gate j keeps
+ * exactly min(ranks[j], r) singular values, r the number of singular values
+ * of its two-site matrix, renormalised as usual; f and the estimate are those
+ * of the rank kept, and no update is flagged as capped.  Replays a run with
+ * given kept ranks (comparison with a reference whose rank decision sits
+ * within rounding of the threshold) and runs fixed-rank schedules.  The
+ * schedule's gate counter advances as usual.  ranks[j] >= 1, else EA_EINVAL
+ * and nothing is applied.  Always host-orchestrated. */
+int mps_apply_layer_ranks(ea_mps *h, int n_gates, const int *sites, const double *ops,
+                          const int *ranks, double *f_out);
+
+/* One layer on each of several independent states.  The paper does not batch
+ * circuits; independent circuits share nothing, so each state receives the
+ * Sec. V-VI updates exactly as from mps_apply_layer.  State b applies
+ * n_gates[b] two-site updates given, as for mps_apply_layer, by sites[b],
+ * ops[b] and budgets[b]
  * (budgets may be NULL, or budgets[b] NULL, for the schedule); f_out may be
  * NULL or hold n_states pointers (each NULL or n_gates[b] doubles).  The
  * states advance concurrently, one host worker per state, each enqueuing on
@@ -306,7 +351,8 @@ int mps_expect(ea_mps *h, int n_terms, const int *sites, const int *widths,
  * matrix (N <= 13), out_complex_len >= 4^N.  EA_ETOOBIG otherwise. */
 int mps_to_statevector(ea_mps *h, double *out, size_t out_complex_len);
 
-/* Bond dimensions chi_1 .. chi_{N-1} into out (n_sites - 1 ints). */
+/* Bond dimensions chi_1 .. chi_{N-1} (Sec. II, Eq. 2; plotted in Figs. 2-4)
+ * into out (n_sites - 1 ints). */
 int mps_bond_dims(const ea_mps *h, int *out);
 
 /* Current orthogonality centre (site index). */

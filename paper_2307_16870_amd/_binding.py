@@ -21,7 +21,7 @@ EA_PURE, EA_MIXED = 0, 1
 EA_C128, EA_C64, EA_C64_BF16X3 = 0, 1, 2
 EA_OK, EA_WARN_CAPPED, EA_WARN_NOCONV = 0, 1, 2
 EA_EINVAL, EA_ERANGE, EA_ENOMEM, EA_EHIP, EA_ETOOBIG = -1, -2, -3, -4, -5
-EA_NAIVE, EA_GLOBAL, EA_NEAREST = 0, 1, 2
+EA_NAIVE, EA_GLOBAL, EA_NEAREST, EA_FIXED = 0, 1, 2, 3
 EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
 EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL, EA_OPT_ROT_THREADS, EA_OPT_REORTH = 5, 6, 7, 8
 EA_OPT_JACOBI_ORDER, EA_OPT_SMALL_LAYERS, EA_OPT_JACOBI_SKIP, EA_OPT_QR_PRECOND = 9, 10, 11, 12
@@ -34,8 +34,14 @@ SYMBOLS = [
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
     "mps_apply_layer_batched", "mps_run_layers_batched", "mps_energy_grad", "ea_last_error",
     "mps_set_tuning", "mps_get_tuning", "mps_program_capture", "mps_program_launch",
-    "mps_program_free",
+    "mps_program_free", "mps_apply_layer_ranks",
 ]
+
+# Lorentzian broadening of the SVD adjoint's 1/(s_j^2 - s_i^2) factors,
+# relative to s_0^4: F = D / (D^2 + ETA_REL_DEFAULT s_0^4), D = s_j^2 - s_i^2.
+# Pairs with |D| >> 1e-6 s_0^2 keep 1/D to a relative 1e-12; closer pairs are
+# damped instead of amplified without bound.
+ETA_REL_DEFAULT = 1e-12
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
                   "jacobi_small", "norms", "trunc", "gather", "gemm", "other", "centre_move", "qr"]
@@ -70,7 +76,16 @@ class GateRecord(ct.Structure):
                 ("chi_m", ct.c_int32), ("chi_r", ct.c_int32), ("k", ct.c_int32),
                 ("k_f", ct.c_int32), ("sweeps", ct.c_int32), ("capped", ct.c_int32),
                 ("f_t", ct.c_double), ("f", ct.c_double), ("total", ct.c_double),
-                ("lnP", ct.c_double)]
+                ("lnP", ct.c_double), ("lnS", ct.c_double)]
+
+
+_ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
+_FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
+
+
+class Allocator(ct.Structure):
+    """ea_allocator: the device-memory source of a handle."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ct.c_void_p)]
 
 
 def load_library(path: str = LIB_PATH) -> ct.CDLL:
@@ -80,13 +95,14 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
     P, I, D, L, S = ct.c_void_p, ct.c_int, ct.c_double, ct.c_long, ct.c_size_t
     dp, ip = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)
     sig = {
-        "mps_init_product": (I, [I, I, I, I, dp, P, ct.POINTER(P)]),
+        "mps_init_product": (I, [I, I, I, I, dp, ct.POINTER(Allocator), P, ct.POINTER(P)]),
         "mps_free": (None, [P]),
         "mps_set_option": (I, [P, I, D]),
         "mps_set_schedule": (I, [P, D, L, I]),
         "mps_apply_1q": (I, [P, I, dp]),
         "mps_apply_2q": (I, [P, I, dp, D, dp]),
         "mps_apply_layer": (I, [P, I, ip, dp, dp, dp]),
+        "mps_apply_layer_ranks": (I, [P, I, ip, dp, ip, dp]),
         "mps_fidelity_estimate": (I, [P, dp, dp]),
         "mps_expect": (I, [P, I, ip, ip, dp, dp]),
         "mps_to_statevector": (I, [P, dp, S]),
@@ -163,13 +179,41 @@ def ea_last_error() -> str:
     return _lib.ea_last_error().decode()
 
 
-def mps_init_product(n_sites, kind=EA_PURE, prec=EA_C128, chi_max=0, local=None, stream=None):
+def _torch_alloc(ctx, nbytes, stream):
+    import torch
+    return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+
+
+def _torch_free(ctx, ptr, stream):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# One process-wide instance: the callbacks must outlive every handle using it.
+_TORCH_ALLOCATOR = Allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+
+
+def torch_allocator():
+    """An ea_allocator drawing device memory from torch's caching allocator
+    (on the stream the library passes: the handle's stream)."""
+    return _TORCH_ALLOCATOR
+
+
+def mps_init_product(n_sites, kind=EA_PURE, prec=EA_C128, chi_max=0, local=None, stream=None,
+                     allocator=None):
+    """allocator: None (hipMalloc), "torch" (torch's caching allocator) or an
+    :class:`Allocator` that outlives the handle."""
     h = ct.c_void_p()
     loc = None
     if local is not None:
         loc = _c(local)
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError(f"unknown allocator {allocator!r}")
+        allocator = _TORCH_ALLOCATOR
     _chk(_lib.mps_init_product(int(n_sites), int(kind), int(prec), int(chi_max),
                                _dp(loc) if loc is not None else None,
+                               ct.byref(allocator) if allocator is not None else None,
                                _stream_handle(stream), ct.byref(h)))
     return h
 
@@ -210,6 +254,23 @@ def mps_apply_layer(h, sites, ops, budgets=None):
     f = np.zeros(len(s))
     rc = _chk(_lib.mps_apply_layer(h, len(s), _ip(s), _dp(o), _dp(b) if b is not None else None,
                                    _dp(f)))
+    return rc, f
+
+
+def mps_apply_layer_ranks(h, sites, ops, ranks):
+    """A layer with every kept rank given.  Returns (status, achieved f per
+    gate in the order given)."""
+    s = np.ascontiguousarray(np.asarray(sites, dtype=np.int32))
+    if len(s) == 0:
+        o = _c(np.zeros((1, 4, 4)))
+    else:
+        o = _c(np.stack([np.asarray(x) for x in ops]) if isinstance(ops, (list, tuple)) else ops)
+    r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32))
+    if r.size != s.size:
+        raise ValueError("one rank per gate")
+    f = np.zeros(len(s))
+    rc = _chk(_lib.mps_apply_layer_ranks(h, len(s), _ip(s), _dp(o), _ip(r) if r.size else None,
+                                         _dp(f)))
     return rc, f
 
 
@@ -437,7 +498,7 @@ def hea_dops(n_qubits, n_layers):
     return ops
 
 
-def mps_energy_grad(h, dops, params, terms, f_min=1.0, eta_rel=0.0):
+def mps_energy_grad(h, dops, params, terms, f_min=1.0, eta_rel=ETA_REL_DEFAULT):
     """E = sum_t c_t Re <O_t> after the circuit, and dE/dparams.  ``dops`` is
     a list for make_dops or its result; ``terms`` a list of (site, width, op,
     coef).  Returns (E, grad, lnP)."""

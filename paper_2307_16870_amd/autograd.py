@@ -27,6 +27,6 @@ class EAEnergy(torch.autograd.Function):
         return grad_out * g.to(grad_out.device, grad_out.dtype), None, None, None, None, None
 
 
-def ea_energy(params, state, dops, terms, f_min=1.0, eta_rel=0.0):
+def ea_energy(params, state, dops, terms, f_min=1.0, eta_rel=B.ETA_REL_DEFAULT):
     """Differentiable E(params) for an ``EAState`` ``state``."""
     return EAEnergy.apply(params, state.h, dops, terms, f_min, eta_rel)

@@ -66,7 +66,7 @@ int mps_get_tuning(int capacity, ea_tune_entry *out) {
 }
 
 int mps_init_product(int n_sites, int kind, int prec, int chi_max, const double *local,
-                     void *hip_stream, ea_mps **out) {
+                     const ea_allocator *alloc, void *hip_stream, ea_mps **out) {
     if (!out) return set_err(EA_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_sites < 2) return set_err(EA_EINVAL, "n_sites must be >= 2");
@@ -77,7 +77,10 @@ int mps_init_product(int n_sites, int kind, int prec, int chi_max, const double 
     const int d = kind == EA_PURE ? 2 : 4;
     if (local && !finite_cplx(local, (size_t)n_sites * d))
         return set_err(EA_EINVAL, "local state has non-finite entries");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return set_err(EA_EINVAL, "allocator needs both alloc and free");
     ea_mps *h = new ea_mps();
+    if (alloc) h->alloc = *alloc;
     h->n = n_sites;
     h->d = d;
     h->kind = kind;
@@ -236,7 +239,7 @@ int mps_set_schedule(ea_mps *h, double f_min, long n_2q_total, int strategy) {
     TRY(check(h));
     if (!(f_min > 0.0 && f_min <= 1.0)) return set_err(EA_EINVAL, "F_min must be in (0, 1]");
     if (n_2q_total < 1) return set_err(EA_EINVAL, "n_2q_total must be >= 1");
-    if (strategy < EA_NAIVE || strategy > EA_NEAREST) return set_err(EA_EINVAL, "bad strategy");
+    if (strategy < EA_NAIVE || strategy > EA_FIXED) return set_err(EA_EINVAL, "bad strategy");
     h->has_sched = true;
     h->f_min = f_min;
     h->n_total = n_2q_total;
@@ -520,6 +523,34 @@ int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
         const double b = budgets ? budgets[j] : -1.0;
         int rc = h->f64 ? apply_2q_impl<double>(h, sites[j], ops + 2 * nop * j, b, asc ? +1 : -1, &f, 0)
                         : apply_2q_impl<float>(h, sites[j], ops + 2 * nop * j, b, asc ? +1 : -1, &f, 0);
+        if (rc < 0) return rc;
+        if (rc > worst) worst = rc;
+        if (f_out) f_out[j] = f;
+    }
+    if (worst > 0) g_err = "warning during layer";
+    return worst;
+}
+
+int mps_apply_layer_ranks(ea_mps *h, int n_gates, const int *sites, const double *ops,
+                          const int *ranks, double *f_out) {
+    int lo = 0, hi = 0;
+    TRY(validate_layer(h, n_gates, sites, ops, nullptr, &lo, &hi));
+    if (n_gates == 0) return EA_OK;
+    if (!ranks) return set_err(EA_EINVAL, "ranks is NULL");
+    for (int j = 0; j < n_gates; ++j)
+        if (ranks[j] < 1) return set_err(EA_EINVAL, "rank %d of gate %d must be >= 1", ranks[j], j);
+    const size_t nop = (size_t)h->d * h->d * h->d * h->d;
+    std::vector<int> order(n_gates);
+    for (int j = 0; j < n_gates; ++j) order[j] = j;
+    const bool asc = std::abs(h->center - lo) <= std::abs(h->center - hi);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        return asc ? sites[a] < sites[b] : sites[a] > sites[b];
+    });
+    int worst = EA_OK;
+    for (int j : order) {
+        double f = 1.0;
+        int rc = h->f64 ? apply_2q_impl<double>(h, sites[j], ops + 2 * nop * j, -1.0, asc ? +1 : -1, &f, ranks[j])
+                        : apply_2q_impl<float>(h, sites[j], ops + 2 * nop * j, -1.0, asc ? +1 : -1, &f, ranks[j]);
         if (rc < 0) return rc;
         if (rc > worst) worst = rc;
         if (f_out) f_out[j] = f;

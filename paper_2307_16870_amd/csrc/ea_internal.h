@@ -36,9 +36,14 @@ inline int set_err(int code, const char *fmt, ...) {
     return code;
 }
 
+// A device buffer.  `al` is the allocator it came from (NULL: hipMalloc) and
+// `stream` the stream it was allocated for, so it can be released without
+// its handle.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    const ea_allocator *al = nullptr;
+    void *stream = nullptr;
 };
 
 }  // namespace ea
@@ -49,6 +54,7 @@ struct ea_mps {
     size_t csz = 16;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    ea_allocator alloc{};    // device memory source (alloc.alloc NULL: hipMalloc / hipFree)
     std::vector<int> bond;  // n+1 entries, bond[0] = bond[n] = 1
     std::vector<ea::DevBuf> site;
     ea::DevBuf spare;
@@ -186,17 +192,33 @@ inline void prof_harvest(ea_mps *h) {
     h->prof_pending.clear();
 }
 
+inline void free_buf(DevBuf &b) {
+    if (b.p) {
+        if (b.al) b.al->free(b.al->ctx, b.p, b.stream);
+        else (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+    b.al = nullptr;
+}
+
+// Grow b to at least `bytes` (x1.25 steps, contents not kept), from the
+// handle's allocator if it has one, else hipMalloc.
 inline int ensure(ea_mps *h, DevBuf &b, size_t bytes) {
     if (bytes <= b.bytes) return EA_OK;
+    const size_t old = b.bytes;
     if (b.p) {
         HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, hipFree(b.p));
-        b.p = nullptr;
-        b.bytes = 0;
+        free_buf(b);
     }
-    size_t want = std::max(bytes, b.bytes + b.bytes / 4);
+    size_t want = std::max(bytes, old + old / 4);
     want = (want + 255) & ~size_t(255);
-    if (hipMalloc(&b.p, want) != hipSuccess) {
+    if (h->alloc.alloc) {
+        b.p = h->alloc.alloc(h->alloc.ctx, want, (void *)h->stream);
+        if (!b.p) return set_err(EA_ENOMEM, "allocator callback returned NULL for %zu bytes", want);
+        b.al = &h->alloc;
+        b.stream = (void *)h->stream;
+    } else if (hipMalloc(&b.p, want) != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
         return set_err(EA_ENOMEM, "hipMalloc(%zu) failed", want);
@@ -263,8 +285,10 @@ inline double schedule_target(const ea_mps *h) {
     } else if (h->strategy == EA_GLOBAL) {
         double left = n - g;
         ft = left <= 0 ? 1.0 : std::exp((std::log(h->f_min) - h->lnP) / left);
-    } else {
+    } else if (h->strategy == EA_NEAREST) {
         ft = std::exp(std::log(h->f_min) * (g + 1) / n - h->lnP);
+    } else {  // EA_FIXED: only the chi_max cap truncates
+        ft = 1.0;
     }
     return std::min(1.0, std::max(ft, 1e-300));
 }
@@ -897,6 +921,7 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
     r.f = rec.f;
     r.total = rec.total;
     r.lnP = h->lnP;
+    r.lnS = h->lnS;
     h->log.push_back(r);
     h->g += 1;
     if (f_out) *f_out = rec.f;
@@ -1148,12 +1173,6 @@ int get_site_impl(ea_mps *h, int site, double *out) {
     HIPCHK(h, hipMemcpyAsync(out, h->c128.p, 16 * sz, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return EA_OK;
-}
-
-inline void free_buf(DevBuf &b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
 }
 
 }  // namespace ea

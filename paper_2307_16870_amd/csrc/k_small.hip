@@ -57,8 +57,10 @@ __device__ double schedule_target_dev(int has_sched, int strategy, double f_min,
     } else if (strategy == EA_GLOBAL) {
         const double left = n - gg;
         ft = left <= 0 ? 1.0 : exp((log(f_min) - lnP) / left);
-    } else {
+    } else if (strategy == EA_NEAREST) {
         ft = exp(log(f_min) * (gg + 1) / n - lnP);
+    } else {  // EA_FIXED: only the chi_max cap truncates
+        ft = 1.0;
     }
     return fmin(1.0, fmax(ft, 1e-300));
 }
@@ -468,6 +470,7 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
                 r.f = dec.f;
                 r.total = dec.total;
                 r.lnP = D.lnP;
+                r.lnS = D.lnS;
                 D.g += 1;
                 if (D.fout) D.fout[j] = dec.f;
                 D.n_capped += dec.capped;

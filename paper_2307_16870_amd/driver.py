@@ -13,13 +13,15 @@ from . import _binding as B
 
 
 class EAState:
-    def __init__(self, n_sites, kind="pure", prec="c128", chi_max=0, local=None, stream=None):
+    def __init__(self, n_sites, kind="pure", prec="c128", chi_max=0, local=None, stream=None,
+                 allocator=None):
+        """allocator: None (hipMalloc) or "torch" (torch's caching allocator)."""
         self.n = int(n_sites)
         self.kind = kind
         self.d = 2 if kind == "pure" else 4
         k = B.EA_PURE if kind == "pure" else B.EA_MIXED
         p = {"c128": B.EA_C128, "c64": B.EA_C64, "bf16x3": B.EA_C64_BF16X3}[prec]
-        self.h = B.mps_init_product(self.n, k, p, chi_max, local, stream)
+        self.h = B.mps_init_product(self.n, k, p, chi_max, local, stream, allocator)
         self.warnings = 0
 
     def close(self):
@@ -54,6 +56,9 @@ class EAState:
 
     def apply_layer(self, sites, ops, budgets=None):
         return B.mps_apply_layer(self.h, sites, ops, budgets)
+
+    def apply_layer_ranks(self, sites, ops, ranks):
+        return B.mps_apply_layer_ranks(self.h, sites, ops, ranks)
 
     def fidelity_estimate(self):
         return B.mps_fidelity_estimate(self.h)
@@ -102,16 +107,42 @@ class EAState:
             self.run_layer(layer)
         return self.warnings
 
-    def run_layer(self, layer):
-        """One-qubit ops of the layer in order, then its two-qubit ops."""
+    def run_layer(self, layer, visit_ranks=None):
+        """One-qubit ops of the layer in order, then its two-qubit ops, with
+        their kept ranks forced if ``visit_ranks`` lists one per two-qubit op
+        in the order the library visits them (as ``gate_log`` records it)."""
         for op in layer:
             if op.width == 1:
                 self.apply_1q(op.site, op.mat)
         twos = [op for op in layer if op.width == 2]
         if twos:
-            rc, _ = self.apply_layer([op.site for op in twos], np.stack([op.mat for op in twos]))
+            sites, mats = [op.site for op in twos], np.stack([op.mat for op in twos])
+            if visit_ranks is None:
+                rc, _ = self.apply_layer(sites, mats)
+            else:
+                # the library visits ascending if the centre is nearer the
+                # lowest site, else descending
+                c = self.center()
+                asc = abs(c - min(sites)) <= abs(c - max(sites))
+                order = sorted(range(len(twos)), key=lambda j: sites[j], reverse=not asc)
+                ranks = [0] * len(twos)
+                for t, j in enumerate(order):
+                    ranks[j] = int(visit_ranks[t])
+                rc, _ = self.apply_layer_ranks(sites, mats, ranks)
             if rc > 0:
                 self.warnings += 1
+
+    def replay(self, program, ranks, f_min=1.0, strategy=B.EA_GLOBAL):
+        """Apply a program with the kept rank of every two-qubit gate given
+        (``ranks`` in visiting order, as ``gate_log`` lists them): the
+        forced-rank replay of a recorded run."""
+        self.set_schedule(f_min, max(1, program.n_2q), strategy)
+        pos = 0
+        for layer in program.layers:
+            n2 = sum(1 for op in layer if op.width == 2)
+            self.run_layer(layer, list(ranks[pos:pos + n2]) if n2 else None)
+            pos += n2
+        return self.warnings
 
 
 def capture_batched(states, programs):

@@ -49,10 +49,17 @@ def test_null_handle_and_last_error():
     assert "null" in P.ea_last_error()
     assert lib.mps_fidelity_estimate(None, None, None) == P.EA_EINVAL
     h = ctypes.c_void_p()
-    assert lib.mps_init_product(1, 0, 0, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
-    assert lib.mps_init_product(4, 7, 0, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
-    assert lib.mps_init_product(4, 0, 9, 0, None, None, ctypes.byref(h)) == P.EA_EINVAL
-    assert lib.mps_init_product(4, 0, 0, -1, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(1, 0, 0, 0, None, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(4, 7, 0, 0, None, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(4, 0, 9, 0, None, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    assert lib.mps_init_product(4, 0, 0, -1, None, None, None, ctypes.byref(h)) == P.EA_EINVAL
+    half = P._binding.Allocator()  # alloc without free
+    half.alloc = P._binding._ALLOC_FN(lambda c, n, s: None)
+    assert lib.mps_init_product(4, 0, 0, 0, None, ctypes.byref(half), None,
+                                ctypes.byref(h)) == P.EA_EINVAL
+    assert "allocator" in P.ea_last_error()
+    assert lib.mps_set_schedule(None, 0.9, 10, P.EA_FIXED) == P.EA_EINVAL
+    assert lib.mps_apply_layer_ranks(None, 0, None, None, None, None) == P.EA_EINVAL
     lib.mps_free(None)
 
 

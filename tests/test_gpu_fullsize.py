@@ -237,3 +237,26 @@ def test_brickwork50_against_oracle_record(prec):
     assert df < tol_f
     assert dlnp < tol_lnp
     assert dobs < tol_obs
+
+
+def test_brickwork50_forced_rank_replay_c64():
+    """Gap rule of the parity protocol: the whole 50-qubit workload replayed
+    in complex FP32 with the oracle record's kept ranks forced
+    (mps_apply_layer_ranks), so every update truncates exactly as the oracle
+    did; every f and the final ln P then agree within the FP32 bar whether or
+    not a rank decision sat inside the rounding margin."""
+    print("case: brickwork50 forced-rank replay c64", flush=True)
+    with open(GOLD) as fh:
+        ref = json.load(fh)
+    prog, c = C.config_program(2)
+    gates = ref["gates"]
+    with P.EAState(prog.n_sites, "pure", "c64", chi_max=c["chi_max"]) as st:
+        st.replay(prog, [r["k"] for r in gates], c["f_min"])
+        glog = st.gate_log()
+        F, lnF = st.fidelity_estimate()
+    assert [g["k"] for g in glog] == [r["k"] for r in gates]
+    assert [g["site"] for g in glog] == [r["site"] for r in gates]
+    df = max(abs(g["f"] - r["f"]) for g, r in zip(glog, gates))
+    print(f"replay c64: max |df| {df:.2e}, |d ln P| {abs(lnF - ref['lnP']):.2e}", flush=True)
+    assert df < 5e-6
+    assert abs(lnF - ref["lnP"]) < 4e-5
