@@ -27,8 +27,10 @@ numerically non-zero singular values), F_ij = 1 / (s_j^2 - s_i^2) (i != j),
   P_ii = sbar_i + i (Im J_ii - Im K_ii) / (2 s_i),
   Abar = U P V^H + (I - U U^H) Ubar S^-1 V^H + U S^-1 Vbar^H (I - V V^H).
 Kept-discarded couplings enter through F_ij with one kept and one discarded
-index; the full spectrum comes from the Jacobi SVD.  ``eta`` > 0 replaces F by
-the Lorentzian (s_j^2 - s_i^2) / ((s_j^2 - s_i^2)^2 + eta).
+index; the full spectrum comes from the Jacobi SVD.  A broadening eta > 0
+replaces F by the Lorentzian (s_j^2 - s_i^2) / ((s_j^2 - s_i^2)^2 + eta), with
+eta = eta_abs + eta_rel s_0^4 (s_0 the largest singular value of the factored
+matrix), so that a relative broadening means the same for every update.
 """
 from __future__ import annotations
 
@@ -41,11 +43,13 @@ from .jacobi import jacobi_svd
 from .mps import truncation_rule
 
 
-def svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta: float = 0.0):
+def svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta: float = 0.0, eta_rel: float = 0.0):
     """Adjoint of A for A = U diag(s) Vh (all r columns non-zero).
 
     U: (m, r), s: (r,), Vh: (r, n); Ubar: (m, r), sbar: (r,), Vbar: (n, r).
+    eta (absolute) and eta_rel (relative to s_0^4) broaden F; both 0: exact.
     """
+    eta = eta + eta_rel * float(np.max(s)) ** 4
     V = Vh.conj().T
     r = s.size
     J = U.conj().T @ Ubar
@@ -79,11 +83,12 @@ def _svd_r(M, tau):
 class AdjointMPS:
     """Pure-state EA-MPS with a tape, for E and dE/d(angles)."""
 
-    def __init__(self, n_sites, chi_max=None, tau=1e-13, eta=0.0):
+    def __init__(self, n_sites, chi_max=None, tau=1e-13, eta=0.0, eta_rel=0.0):
         self.n = n_sites
         self.chi_max = chi_max
         self.tau = tau
         self.eta = eta
+        self.eta_rel = eta_rel
         self.A: List[np.ndarray] = []
         for _ in range(n_sites):
             a = np.zeros((1, 2, 1), dtype=np.complex128)
@@ -182,7 +187,7 @@ class AdjointMPS:
         Ab = [np.zeros_like(a) for a in self.A]
         grad = np.zeros(n_angles)
         for rec in reversed(self.tape):
-            _reverse_record(rec, Ab, grad, self.eta)
+            _reverse_record(rec, Ab, grad, self.eta, self.eta_rel)
         return grad
 
 
@@ -197,7 +202,7 @@ def _dgate(kind, g):
     raise ValueError(kind)
 
 
-def _reverse_record(rec, Ab, grad, eta):
+def _reverse_record(rec, Ab, grad, eta, eta_rel):
     """Vector-Jacobian product of one recorded step, in place on the site
     adjoints ``Ab`` (and ``grad`` for tagged angles)."""
     kind = rec[0]
@@ -234,7 +239,7 @@ def _reverse_record(rec, Ab, grad, eta):
         Vbar[:, :k] = st[None, :] * bbar.T.conj()
         sbar = np.zeros(r)                                  # s~ = s_k / ||s_k||
         sbar[:k] = stbar / sig - s[:k] * np.dot(stbar, s[:k]) / sig ** 3
-        thbar = svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta)
+        thbar = svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta, eta_rel)
         # Theta = G (A B):  Cbar = G^H Thetabar, Abar = Cbar B^H, Bbar = A^H Cbar
         Cb = np.einsum("stuv,lstr->luvr", G.reshape(2, 2, 2, 2).conj(),
                        thbar.reshape(chi_l, 2, 2, chi_r))
@@ -251,7 +256,7 @@ def _reverse_record(rec, Ab, grad, eta):
         V = Vh.conj().T
         sbar = np.real(np.einsum("jc,cj->j", Xbar, V))       # X = S V^H
         Vbar = s[None, :] * Xbar.T.conj()
-        Ab[c] = svd_vjp(U, s, Vh, Ab[c].reshape(cl * d, r), sbar, Vbar, eta).reshape(a.shape)
+        Ab[c] = svd_vjp(U, s, Vh, Ab[c].reshape(cl * d, r), sbar, Vbar, eta, eta_rel).reshape(a.shape)
     elif kind == "ml":
         _, c, a, b, U, s, Vh = rec
         cl, d, cr = a.shape
@@ -263,13 +268,13 @@ def _reverse_record(rec, Ab, grad, eta):
         Ubar = Ybar * s[None, :]                              # Y = U S
         sbar = np.real(np.einsum("rj,rj->j", U.conj(), Ybar))
         Vbar = Ab[c].reshape(r, d * cr).T.conj()               # A_c' = V^H
-        Ab[c] = svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta).reshape(a.shape)
+        Ab[c] = svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta, eta_rel).reshape(a.shape)
     else:
         raise ValueError(kind)
 
 
 def hea_energy_and_grad(angles, terms, f_min=None, chi_max=None, forced_ranks=None, eta=0.0,
-                        tau=1e-13):
+                        tau=1e-13, eta_rel=0.0):
     """E = sum_t c_t Re <O_t> after the hardware-efficient ansatz (per layer:
     RY then RZ on every qubit, then CZ on brickwork pairs) run by EA-MPS with
     the global schedule for F_min, and dE/d(angles).
@@ -278,7 +283,7 @@ def hea_energy_and_grad(angles, terms, f_min=None, chi_max=None, forced_ranks=No
     """
     from circuits import ry, rz, CZ, brickwork_pairs
     L, n, _ = angles.shape
-    sim = AdjointMPS(n, chi_max=chi_max, tau=tau, eta=eta)
+    sim = AdjointMPS(n, chi_max=chi_max, tau=tau, eta=eta, eta_rel=eta_rel)
     if f_min is not None:
         sim.f_min = f_min
         sim.n_total = sum(len(brickwork_pairs(n, l)) for l in range(L))

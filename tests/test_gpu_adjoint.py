@@ -15,7 +15,8 @@ def test_energy_grad_small_vs_oracle(n, L, f_min):
     print("case: adjoint small", n, L, f_min, flush=True)
     angles = C.hea_angles(n, L, seed=7)
     terms = C.hea_hamiltonian(n)
-    Eo, go, ranks, lnPo = hea_energy_and_grad(angles, terms, f_min=None if f_min >= 1 else f_min)
+    Eo, go, ranks, lnPo = hea_energy_and_grad(angles, terms, f_min=None if f_min >= 1 else f_min,
+                                              eta_rel=P.ETA_REL_DEFAULT)
     with P.EAState(n, "pure", "c128") as st:
         E, g, lnP = P.mps_energy_grad(st.h, P.hea_dops(n, L), angles, terms, f_min=f_min)
         ks = [r["k"] for r in st.gate_log()]
@@ -25,13 +26,36 @@ def test_energy_grad_small_vs_oracle(n, L, f_min):
     np.testing.assert_allclose(g, go.reshape(-1), atol=1e-10)
 
 
+@pytest.mark.parametrize("eta_rel", [1e-6, 1e-3])
+def test_energy_grad_broadened_vs_oracle(eta_rel):
+    """Strong Lorentzian broadening (pairs with s_j^2 - s_i^2 below about
+    sqrt(eta_rel) s_0^2 damped, among them the exactly degenerate values the
+    CZ gates leave at F_min = 1): the GPU adjoint equals the FP64 adjoint
+    oracle run with the same eta_rel, and differs from the exact one."""
+    print("case: adjoint broadened", eta_rel, flush=True)
+    n, L = 6, 3
+    angles = C.hea_angles(n, L, seed=7)
+    terms = C.hea_hamiltonian(n)
+    Eo, go, ranks, _ = hea_energy_and_grad(angles, terms, f_min=0.999, eta_rel=eta_rel)
+    _, g_exact, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999)
+    with P.EAState(n, "pure", "c128") as st:
+        E, g, _ = P.mps_energy_grad(st.h, P.hea_dops(n, L), angles, terms, f_min=0.999,
+                                    eta_rel=eta_rel)
+        ks = [r["k"] for r in st.gate_log()]
+    assert ks == ranks
+    assert abs(E - Eo) < 1e-10
+    np.testing.assert_allclose(g, go.reshape(-1), atol=1e-10)
+    assert np.abs(go - g_exact).max() > 1e-8  # the broadening is in effect
+
+
 def test_energy_grad_hea32_vs_oracle():
     """The 32-qubit, 10-layer hardware-efficient ansatz, F_min = 0.999:
     energy and all 640 angle derivatives within 1e-10 of the FP64 oracle."""
     print("case: adjoint hea32", flush=True)
     angles = C.hea_angles(32, 10, seed=5)
     terms = C.hea_hamiltonian(32)
-    Eo, go, ranks, lnPo = hea_energy_and_grad(angles, terms, f_min=0.999)
+    Eo, go, ranks, lnPo = hea_energy_and_grad(angles, terms, f_min=0.999,
+                                              eta_rel=P.ETA_REL_DEFAULT)
     with P.EAState(32, "pure", "c128") as st:
         E, g, lnP = P.mps_energy_grad(st.h, P.hea_dops(32, 10), angles, terms, f_min=0.999)
         ks = [r["k"] for r in st.gate_log()]
@@ -45,7 +69,7 @@ def test_energy_grad_fp32_tolerance():
     print("case: adjoint fp32", flush=True)
     angles = C.hea_angles(10, 4, seed=3)
     terms = C.hea_hamiltonian(10)
-    Eo, go, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999)
+    Eo, go, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999, eta_rel=P.ETA_REL_DEFAULT)
     with P.EAState(10, "pure", "c64") as st:
         E, g, _ = P.mps_energy_grad(st.h, P.hea_dops(10, 4), angles, terms, f_min=0.999)
     assert abs(E - Eo) < 1e-4
@@ -58,7 +82,7 @@ def test_autograd_function():
     from paper_2307_16870_amd.autograd import ea_energy
     angles = C.hea_angles(6, 3, seed=9)
     terms = C.hea_hamiltonian(6)
-    Eo, go, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999)
+    Eo, go, _, _ = hea_energy_and_grad(angles, terms, f_min=0.999, eta_rel=P.ETA_REL_DEFAULT)
     p = torch.tensor(angles, dtype=torch.float64, requires_grad=True)
     with P.EAState(6, "pure", "c128") as st:
         E = ea_energy(p, st, P.hea_dops(6, 3), terms, f_min=0.999)

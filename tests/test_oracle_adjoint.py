@@ -133,7 +133,7 @@ def test_planted_mistakes_are_caught(mistake, monkeypatch):
     import oracle.adjoint as adj
     real = adj.svd_vjp
 
-    def broken(U, s, Vh, Ubar, sbar, Vbar, eta=0.0):
+    def broken(U, s, Vh, Ubar, sbar, Vbar, eta=0.0, eta_rel=0.0):
         if mistake == "drop_projection":
             V = Vh.conj().T
             J = U.conj().T @ Ubar
@@ -146,15 +146,15 @@ def test_planted_mistakes_are_caught(mistake, monkeypatch):
             P[np.diag_indices(s.size)] = sbar + 1j * (np.imag(np.diag(J)) - np.imag(np.diag(K))) / (2 * s)
             return U @ P @ Vh
         if mistake == "wrong_F_sign":
-            return real(U, s, Vh, Ubar, sbar, Vbar, eta) - 2 * (
-                real(U, s, Vh, Ubar, sbar, Vbar, eta)
-                - real(U, s, Vh, np.zeros_like(Ubar), sbar, np.zeros_like(Vbar), eta))
+            return real(U, s, Vh, Ubar, sbar, Vbar, eta, eta_rel) - 2 * (
+                real(U, s, Vh, Ubar, sbar, Vbar, eta, eta_rel)
+                - real(U, s, Vh, np.zeros_like(Ubar), sbar, np.zeros_like(Vbar), eta, eta_rel))
         if mistake == "drop_phase_term":
             V = Vh.conj().T
             J = U.conj().T @ Ubar
             K = V.conj().T @ Vbar
             extra = U @ np.diag(1j * (np.imag(np.diag(J)) - np.imag(np.diag(K))) / (2 * s)) @ Vh
-            return real(U, s, Vh, Ubar, sbar, Vbar, eta) - extra
+            return real(U, s, Vh, Ubar, sbar, Vbar, eta, eta_rel) - extra
         raise ValueError(mistake)
 
     monkeypatch.setattr(adj, "svd_vjp", broken)
@@ -173,3 +173,83 @@ def test_planted_mistakes_are_caught(mistake, monkeypatch):
         Em = adj.hea_energy_and_grad(am.reshape(angles.shape), terms, f_min=0.99, forced_ranks=ranks)[0]
         worst = max(worst, abs(g.reshape(-1)[j] - (Ep - Em) / (2 * h)))
     assert worst > 1e-4, f"planted mistake {mistake} not detected (worst {worst})"
+
+
+def test_svd_vjp_near_degenerate_lorentzian():
+    """A spectrum with two kept singular values 1e-5 apart (D = s_1^2 - s_2^2
+    = 1.2e-5 s_0^2).  Exact branch (eta = 0): the gauge-free loss's
+    derivative matches central differences.  Broadened branch: the only term
+    that eta changes appreciably is the near-degenerate pair's, scaled by
+    D^2 / (D^2 + eta), so the bias g_eta - g_FD along one direction must
+    follow eta / (D^2 + eta) between two broadenings (the next-closest pair
+    has D = 0.05 s_0^2, whose change is below 1e-9 relative)."""
+    rng = np.random.default_rng(4)
+    m, n, k = 9, 7, 4
+
+    def haar(n_):
+        Z = rng.standard_normal((n_, n_)) + 1j * rng.standard_normal((n_, n_))
+        Q, R = np.linalg.qr(Z)
+        return Q * (np.diag(R) / abs(np.diag(R)))
+
+    s_true = np.array([1.0, 0.6 + 1e-5, 0.6, 0.3, 0.2, 0.1, 0.05])
+    A = (haar(m)[:, :n] * s_true) @ haar(n).conj().T
+    Wt = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    Wq = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+
+    def f(A):
+        r = jacobi_svd(A)
+        U, s, Vh = r.u[:, :k], r.s[:k], r.vh[:k]
+        T = (U * (s / np.linalg.norm(s))) @ Vh
+        return float(np.real(np.vdot(Wt, T)) + np.real(np.vdot(Wq, U @ U.conj().T)))
+
+    r = jacobi_svd(A)
+    U, s, Vh = r.u, r.s, r.vh
+    V = Vh.conj().T
+    sig = np.linalg.norm(s[:k])
+    st = s[:k] / sig
+    Ubar = np.zeros_like(U)
+    Vbar = np.zeros_like(V)
+    Ubar[:, :k] = Wt @ V[:, :k] * st[None, :] + (Wq + Wq.conj().T) @ U[:, :k]
+    Vbar[:, :k] = Wt.conj().T @ U[:, :k] * st[None, :]
+    stbar = np.real(np.einsum("ij,ij->j", U[:, :k].conj(), Wt @ V[:, :k]))
+    sbar = np.zeros(s.size)
+    sbar[:k] = stbar / sig - s[:k] * np.dot(stbar, s[:k]) / sig ** 3
+    D = s[1] ** 2 - s[2] ** 2
+    assert 1.1e-5 < D < 1.3e-5
+    etas = (1e-14, 1e-12)
+    g0 = svd_vjp(U, s, Vh, Ubar, sbar, Vbar)
+    ge = [svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta_rel=e) for e in etas]
+    for _ in range(3):
+        Dd = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+        h = 1e-7
+        fd = (f(A + h * Dd) - f(A - h * Dd)) / (2 * h)
+        a0 = float(np.real(np.vdot(g0, Dd)))
+        assert abs(a0 - fd) < 1e-6 * max(1.0, abs(a0)), (a0, fd)
+        bias = [float(np.real(np.vdot(g, Dd))) - a0 for g in ge]
+        law = [e / (D * D + e) for e in etas]  # s_0 = 1
+        assert abs(bias[0] / bias[1] - law[0] / law[1]) < 1e-3 * law[0] / law[1], (bias, law)
+        # and the broadened value stays within that bias of the finite difference
+        assert abs(a0 + bias[1] - fd) <= abs(bias[1]) + 1e-6 * max(1.0, abs(a0))
+
+
+def test_svd_vjp_lorentzian_bounded_at_a_cut_inside_a_degenerate_pair():
+    """Exactly equal singular values on both sides of the cut: the exact
+    F = 1/D is unbounded (taken as 0 at D = 0 exactly), the broadened one is
+    bounded by 1 / (2 sqrt(eta)).  With D at rounding level the broadened
+    adjoint stays finite and within that bound times the numerators."""
+    rng = np.random.default_rng(8)
+    m, n = 6, 5
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    s_true = np.array([1.0, 0.5, 0.5 * (1 + 1e-15), 0.2, 0.1])
+    A = (Q1[:, :n] * s_true) @ Q2.conj().T
+    r = jacobi_svd(A)
+    U, s, Vh = r.u, r.s, r.vh
+    Ubar = rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape)
+    Vbar = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    sbar = rng.standard_normal(n)
+    eta_rel = 1e-12
+    g = svd_vjp(U, s, Vh, Ubar, sbar, Vbar, eta_rel=eta_rel)
+    assert np.all(np.isfinite(g))
+    # every F entry is at most 1/(2 sqrt(eta)) = 5e5; numerators are O(10)
+    assert np.abs(g).max() < 1e8
