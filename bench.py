@@ -139,28 +139,97 @@ def run_circuit(st, prog, f_min, progress=False):
             log(f"  layer {li} done at {time.perf_counter() - t0:.1f}s")
 
 
-def cpu_baseline(prog, f_min, chi_max, n_layers, budget_s):
-    import numpy as np  # noqa: F401
+def _timed_oracle(prog, chi_max, svd):
+    """The oracle with every two-site update (its centre moves included)
+    timed: records (seconds, d, chi_l, chi_r)."""
     from oracle.mps import OracleMPS
-    o = OracleMPS(prog.n_sites, "pure", chi_max=chi_max)
-    o.set_schedule(f_min, prog.n_2q)
-    t0 = time.perf_counter()
-    n_upd = 0
+
+    class TimedOracle(OracleMPS):
+        def apply_2q(self, i, G, f_t=None, direction="right", forced_k=None):
+            t0 = time.perf_counter()
+            rec = super().apply_2q(i, G, f_t, direction, forced_k)
+            self.times.append((time.perf_counter() - t0, self.d, rec.chi_l, rec.chi_r))
+            return rec
+
+    o = TimedOracle(prog.n_sites, "pure", chi_max=chi_max, svd=svd)
+    o.times = []
+    return o
+
+
+def _update_cost(d, chi_l, chi_r):
+    """Cost model of one update on the CPU: the SVD of the (d chi_l) x
+    (d chi_r) two-site matrix, m n min(m, n) (the contraction and the move
+    scale the same way at equal bonds)."""
+    m, n = d * chi_l, d * chi_r
+    return float(m) * n * min(m, n)
+
+
+def cpu_baseline(prog, f_min, chi_max, n_layers, budget_s, gpu_log=None, gpu_prefix_s=None):
+    """The oracle (complex128, its own one-sided Jacobi SVD, all host cores)
+    on the first layers of the same circuit, and beside it the same oracle
+    with LAPACK's SVD (the fair CPU speed baseline) on the same layers.  The
+    GPU's time for the same layers is reported next to it.  From the
+    per-update times, binned by (d, chi_l, chi_r), a fitted a + b m n min(m, n)
+    model extrapolates the oracle to the whole circuit (labelled as such)."""
+    import numpy as np
+    legs = {}
     used = 0
-    for layer in prog.layers[:n_layers]:
-        o.apply_layer(layer)
-        n_upd += len(layer)
-        used += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    for svd in ("auto", "lapack"):
+        o = _timed_oracle(prog, chi_max, svd)
+        o.set_schedule(f_min, prog.n_2q)
+        t0 = time.perf_counter()
+        n_upd = 0
+        layers = prog.layers[:n_layers] if svd == "auto" else prog.layers[:used]
+        for layer in layers:
+            o.apply_layer(layer)
+            n_upd += len(layer)
+            if svd == "auto":
+                used += 1
+                if time.perf_counter() - t0 > budget_s:
+                    break
+        dt = time.perf_counter() - t0
+        legs[svd] = {"seconds": dt, "updates": n_upd, "times": o.times,
+                     "max_bond": max(o.bond_dims())}
+    jac = legs["auto"]
     cores = len(os.sched_getaffinity(0))
-    return {
-        "value": n_upd / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
-        "sample": (f"first {used} of {len(prog.layers)} layers ({n_upd} of {prog.n_2q} updates, "
-                   f"bonds up to {max(o.bond_dims())}) of the same circuit; complex128 oracle "
-                   f"with its own one-sided Jacobi SVD; {dt:.1f} s"),
+    out = {
+        "value": jac["updates"] / jac["seconds"], "unit": "updates/s", "cores": cores,
+        "kind": "oracle",
+        "sample": (f"first {used} of {len(prog.layers)} layers ({jac['updates']} of {prog.n_2q} "
+                   f"updates, bonds up to {jac['max_bond']}) of the same circuit; complex128 "
+                   f"oracle with its own one-sided Jacobi SVD; {jac['seconds']:.1f} s"),
+        "lapack": {"value": legs["lapack"]["updates"] / legs["lapack"]["seconds"],
+                   "unit": "updates/s",
+                   "sample": f"the same {used} layers, the oracle with LAPACK's SVD "
+                             f"(numpy.linalg.svd); {legs['lapack']['seconds']:.1f} s"},
     }
+    if gpu_prefix_s is not None:
+        out["gpu_same_sample"] = {"value": jac["updates"] / gpu_prefix_s, "unit": "updates/s",
+                                  "seconds": gpu_prefix_s,
+                                  "sample": f"the GPU path on the same {used} layers"}
+    if gpu_log:
+        # per-update CPU cost extrapolated to the whole circuit with the GPU
+        # run's bonds (same schedule, same ranks up to rounding)
+        for name, leg in (("extrapolated_oracle", jac), ("extrapolated_lapack", legs["lapack"])):
+            t = np.array([x[0] for x in leg["times"]])
+            c = np.array([_update_cost(*x[1:]) for x in leg["times"]])
+            # least squares t = a + b c over per-(d, chi_l, chi_r) bin means
+            bins = {}
+            for ti, x in zip(t, leg["times"]):
+                bins.setdefault(x[1:], []).append(ti)
+            cb = np.array([_update_cost(*k) for k in bins])
+            tb = np.array([np.mean(v) for v in bins.values()])
+            A = np.stack([np.ones_like(cb), cb], axis=1)
+            (a, b), *_ = np.linalg.lstsq(A, tb, rcond=None)
+            a, b = max(a, 0.0), max(b, 1e-30)
+            full = sum(a + b * _update_cost(2, r["chi_l"], r["chi_r"]) for r in gpu_log)
+            out[name] = {"value": len(gpu_log) / full, "unit": "updates/s",
+                         "circuit_s": full, "label": "extrapolated",
+                         "model": f"t = {a:.3e} s + {b:.3e} s * m n min(m, n), fitted on "
+                                  f"{len(bins)} (d, chi_l, chi_r) bins of the sample, "
+                                  f"m = d chi_l, n = d chi_r, applied to every update of the "
+                                  f"GPU run (sweep counts growing with n not modelled)"}
+    return out
 
 
 def bench_batched(args, torch, C, P):
@@ -295,6 +364,127 @@ def bench_hea32(args, torch, C, P):
     print(json.dumps(out), flush=True)
 
 
+def _exact_statevector_torch(torch, prog):
+    """Reference |psi> of a noiseless program by plain dense state-vector
+    simulation (torch complex128 on the GPU), for the true fidelity of the
+    strategy study: not part of the simulator under test."""
+    n = prog.n_sites
+    psi = torch.zeros(2 ** n, dtype=torch.complex128, device="cuda")
+    psi[0] = 1.0
+    for op in prog.ops():
+        g = torch.as_tensor(op.mat, dtype=torch.complex128, device="cuda")
+        w = 2 ** op.width
+        left = 2 ** op.site
+        v = psi.view(left, w, -1)
+        psi = torch.einsum("ab,lbr->lar", g, v).reshape(-1)
+    return psi
+
+
+def bench_fig1(args, torch, C, P):
+    """Strategy study (Sec. VI, Fig. 1 analogue): 25 qubits, brickwork Haar
+    depth 20, complex FP64; per F_min in {0.9, 0.99} and per strategy (naive,
+    nearest, global) the final estimate P against the true fidelity
+    |<psi_exact|psi>|^2 from a dense state vector, with the peak bond and the
+    wall time."""
+    import numpy as np
+    n, depth = 25, 20
+    prog = C.brickwork_program(n, depth, 2307)
+    t0 = time.perf_counter()
+    ref = _exact_statevector_torch(torch, prog)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    ref = ref.cpu().numpy()
+    rows = []
+    names = {P.EA_NAIVE: "naive", P.EA_NEAREST: "nearest", P.EA_GLOBAL: "global"}
+    for f_min in (0.9, 0.99):
+        for strat in (P.EA_NAIVE, P.EA_NEAREST, P.EA_GLOBAL):
+            with P.EAState(n, "pure", "c128") as st:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st.run(prog, f_min, strategy=strat)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                F, _ = st.fidelity_estimate()
+                psi = st.statevector()
+                bonds = [max(r["chi_l"], r["k"]) for r in st.gate_log()]
+            psi = psi / np.linalg.norm(psi)
+            true = float(abs(np.vdot(ref, psi)) ** 2)
+            rows.append({"f_min": f_min, "strategy": names[strat], "estimate": F,
+                         "true_fidelity": true, "peak_bond": int(max(bonds)),
+                         "seconds": dt, "updates": prog.n_2q})
+            log(f"fig1 F_min={f_min} {names[strat]}: P={F:.5f} true={true:.5f} "
+                f"peak bond {max(bonds)} {dt:.2f}s")
+    print(json.dumps({"study": "fig1-strategies-25q-depth20", "reference_seconds": t_ref,
+                      "rows": rows}), flush=True)
+
+
+def bench_fig2a(args, torch, C, P):
+    """Mirror circuit (Sec. VI, Fig. 2a analogue): 40 qubits, a brickwork Haar
+    circuit of depth 10 followed by its inverse, complex FP64, F_min in
+    {1 - 1e-6, 0.99}: the largest bond after every layer (entanglement grows,
+    then falls back), the final estimate and <Z_i> at the end (all 1 for the
+    exact identity)."""
+    import numpy as np
+    n, depth = 40, 10
+    prog = C.mirror_program(n, depth, 40)
+    rows = []
+    for f_min in (1 - 1e-6, 0.99):
+        with P.EAState(n, "pure", "c128") as st:
+            st.set_schedule(f_min, prog.n_2q)
+            peaks = []
+            t1 = time.perf_counter()
+            for layer in prog.layers:
+                st.run_layer(layer)
+                peaks.append(int(max(st.bond_dims())))
+            dt = time.perf_counter() - t1
+            F, _ = st.fidelity_estimate()
+            z = np.real(st.expect(list(range(n)), [1] * n, [np.diag([1.0, -1.0])] * n))
+        rows.append({"f_min": f_min, "max_bond_per_layer": peaks, "estimate": F,
+                     "min_Z": float(z.min()), "final_max_bond": peaks[-1], "seconds": dt})
+        log(f"fig2a F_min={f_min}: peaks {peaks} P={F:.6f} min<Z>={z.min():.6f}")
+    print(json.dumps({"study": "fig2a-mirror-40q-depth10x2", "rows": rows}), flush=True)
+
+
+def bench_fig4(args, torch, C, P):
+    """Entanglement-aware against fixed-bond-dimension simulation (Sec. VI,
+    Fig. 4 analogue, scaled down): the EA run with F_min, then the standard
+    run (every target 1, only the cap truncates) with chi_max = the largest
+    bond of the EA run.  Noiseless: 32 qubits, depth 32, F_min 0.99, complex
+    FP32.  Noisy MPO: 16 qubits, depth 16, two-qubit depolarising p = 1e-3,
+    F_min 0.95, complex FP32.  Wall time, final estimate, peak bond, and the
+    sum over updates of chi_l chi_r (bond-size work)."""
+    rows = []
+    for kind, n, depth, f_min, noise in (("pure", 32, 32, 0.99, 0.0),
+                                         ("mixed", 16, 16, 0.95, 1e-3)):
+        prog = C.brickwork_program(n, depth, 75, kind=kind, noise_p=noise)
+        res = {}
+        chi_ea = None
+        for mode in ("ea", "fixed"):
+            chi_max = 0 if mode == "ea" else chi_ea
+            with P.EAState(n, kind, args.prec, chi_max=chi_max) as st:
+                run_circuit(st, C.brickwork_program(n, 2, 1, kind=kind, noise_p=noise), 1.0)
+                st.reset()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st.run(prog, f_min, strategy=P.EA_GLOBAL if mode == "ea" else P.EA_FIXED)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                F, _ = st.fidelity_estimate()
+                glog = st.gate_log()
+            peak = max(r["k"] for r in glog)
+            if mode == "ea":
+                chi_ea = peak
+            res[mode] = {"seconds": dt, "estimate": F, "peak_bond": int(peak),
+                         "chi_work": float(sum(r["chi_l"] * r["chi_r"] for r in glog)),
+                         "capped_updates": int(sum(r["capped"] for r in glog))}
+            log(f"fig4 {kind} {mode}: {dt:.2f}s P={F:.5f} peak {peak}")
+        rows.append({"kind": kind, "n_qubits": n, "depth": depth, "f_min": f_min,
+                     "noise_p": noise, "chi_max_fixed": chi_ea, **res,
+                     "speedup_ea_vs_fixed": res["fixed"]["seconds"] / res["ea"]["seconds"]})
+    print(json.dumps({"study": "fig4-ea-vs-fixed-chi", "prec": args.prec, "rows": rows}),
+          flush=True)
+
+
 def bench_contraction(args, torch, C, P):
     """The two-site contraction with the gate (one launch per update) alone, at
     chi = 256, 512 and 1024 (Theta up to 2048 x 2048, K = chi), in every
@@ -351,11 +541,14 @@ def main():
     ap.add_argument("--cpu-layers", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--workload", default="brickwork50",
-                    choices=["brickwork50", "batched", "mpo40", "hea32", "contraction"],
+                    choices=["brickwork50", "batched", "mpo40", "hea32", "contraction",
+                             "fig1", "fig2a", "fig4"],
                     help="brickwork50: the 50-qubit depth-20 circuit (default); batched: "
                          "independent circuits of the batched workload advanced together; "
                          "mpo40: the noisy 40-qubit MPO circuit; hea32: adjoint gradients; "
-                         "contraction: the two-site contraction alone at chi <= 1024")
+                         "contraction: the two-site contraction alone at chi <= 1024; "
+                         "fig1 / fig2a / fig4: the paper's strategy, mirror-circuit and "
+                         "EA-against-fixed-bond studies at reduced sizes")
     ap.add_argument("--circuits", type=int, default=16, help="batched: number of circuits")
     ap.add_argument("--max-depth", type=int, default=12, help="batched: depth cap per circuit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -387,6 +580,9 @@ def main():
         return bench_hea32(args, torch, C, P)
     if args.workload == "contraction":
         return bench_contraction(args, torch, C, P)
+    if args.workload in ("fig1", "fig2a", "fig4"):
+        return {"fig1": bench_fig1, "fig2a": bench_fig2a, "fig4": bench_fig4}[args.workload](
+            args, torch, C, P)
     stream = torch.cuda.current_stream()
     prog, cfg = C.config_program(2, depth=args.depth)
     f_min, chi_max = cfg["f_min"], cfg["chi_max"]
@@ -412,6 +608,7 @@ def main():
 
     F, lnF = st.fidelity_estimate()
     glog = st.gate_log()
+    glog_full = glog[-prog.n_2q:]  # the last timed step's updates
     n_upd = prog.n_2q * args.steps
     ms_step = 1000.0 * elapsed / args.steps
     log(f"elapsed {elapsed:.2f}s  P={F:.5f}")
@@ -458,13 +655,36 @@ def main():
                    "f_min": f_min, "chi_max": chi_max, "schedule": "global", "prec": args.prec},
         "circuit_time_s": ms_step / 1000.0,
         "final_fidelity_estimate": F,
-        "capped_updates": int(sum(r["capped"] for r in glog)),
+        "capped_updates": int(sum(r["capped"] for r in glog_full)),
+        "meets_f_min": bool(F >= f_min),
+        "f_min_note": ("the bond cap of 1024 binds before the end of this circuit: capped "
+                       "updates keep less weight than their target, so the estimate ends "
+                       "below F_min" if F < f_min else "estimate at or above F_min"),
         "max_bond": int(max(st.bond_dims())),
         "kernels_ms": {k: round(v["ms"], 3) for k, v in fams.items()},
         "roofline": roofline,
         "rooflines_other": {k: roof(k) for k in ["jacobi_apply", "jacobi_gram", "theta"]
                             if fams[k]["launches"] > 0 and k != dom},
     }
+    # the Jacobi SVD of the two-site updates as a whole: (18 m n^2 + 14 n^3)
+    # flops per sweep (the per-sweep count of a one-sided Jacobi in its
+    # real-arithmetic form; complex arithmetic executes about four times as
+    # many), m x n the factored matrix, over every update's sweeps, against
+    # the time of all Jacobi kernel families
+    jac_fl = 0.0
+    for r in glog_full:
+        mw, nw = 2 * max(r["chi_l"], r["chi_r"]), 2 * min(r["chi_l"], r["chi_r"])
+        jac_fl += r["sweeps"] * (18.0 * mw * nw * nw + 14.0 * nw ** 3)
+    jac_fl *= args.steps
+    jac_ms = sum(fams[k]["ms"] for k in ("jacobi_gram", "jacobi_rot", "jacobi_apply",
+                                         "jacobi_small", "jacobi_fused"))
+    if jac_ms > 0:
+        ach = jac_fl / (jac_ms * 1e-3) / 1e12
+        out["rooflines_other"]["jacobi_svd_all"] = {
+            "kernels": "k_jgram + k_jeig + k_japply + k_jacobi_block", "bound": "mfma",
+            "achieved": ach, "peak": mfma_peak, "unit": "TFLOP/s", "frac": ach / mfma_peak,
+            "count": "sum over updates of sweeps x (18 m n^2 + 14 n^3)",
+            "device_ms": jac_ms}
     if not args.no_fp64 and args.prec != "c128":
         log("fp64 comparison step")
         st64 = P.EAState(prog.n_sites, "pure", "c128", chi_max=chi_max, stream=stream)
@@ -481,8 +701,21 @@ def main():
         st64.close()
     st.close()
     if not args.no_cpu:
+        # the GPU on the oracle's sample: the first cpu_layers layers
+        st2 = P.EAState(prog.n_sites, "pure", args.prec, chi_max=chi_max, stream=stream)
+        run_circuit(st2, tiny, 1.0)
+        st2.reset()
+        st2.set_schedule(f_min, prog.n_2q)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for layer in prog.layers[:args.cpu_layers]:
+            st2.run_layer(layer)
+        torch.cuda.synchronize()
+        tpre = time.perf_counter() - t1
+        st2.close()
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(prog, f_min, chi_max, args.cpu_layers, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(prog, f_min, chi_max, args.cpu_layers, args.cpu_budget,
+                                           gpu_log=glog_full, gpu_prefix_s=tpre)
     print(json.dumps(out), flush=True)
 
 

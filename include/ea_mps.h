@@ -128,15 +128,20 @@ enum ea_option {
                                 examined (it would find the same Gram matrix and no
                                 rotation, so results are bit-identical); 0 examines every
                                 pair in every sweep */
-    EA_OPT_QR_MOVES = 13,    /* 1: centre moves of the update path by Householder QR
-                                (A_c = Q R, Q the new site, R absorbed into the neighbour;
-                                Sec. III), no rank dropped; 0: by the Jacobi SVD, dropping
-                                numerically zero singular values.  The gradient path
-                                (mps_energy_grad) always moves by SVD. */
+    EA_OPT_QR_MOVES = 13,    /* centre moves of the update path (Sec. III): 2 (default):
+                                Cholesky QR2 in FP64 (A_c = Q R, Q the new site, R absorbed
+                                into the neighbour; matrix-core GEMMs and a blocked
+                                Cholesky), no rank dropped; a site whose condition number
+                                exceeds about 1e7 (a Cholesky pivot below 1e-14 of the
+                                largest diagonal entry), or whose matrix is wider than
+                                tall, moves by the Jacobi SVD instead.  1: Householder QR,
+                                no rank dropped.  0: the Jacobi SVD, dropping numerically
+                                zero singular values.  The gradient path (mps_energy_grad)
+                                always moves by SVD. */
     EA_OPT_QR_PRECOND = 12   /* w > 0: a factorisation of at least w columns on the
                                 three-kernel Jacobi first takes the Householder QR of its
                                 matrix (Theta = Q R, panels on one workgroup each, trailing
-                                updates and products with Q as rocBLAS GEMMs) and runs the
+                                updates and products with Q as matrix-core GEMMs) and runs the
                                 Jacobi on R^H, whose columns are nearer orthogonal (fewer
                                 sweeps); the SVD of Theta is then (Q V_x) S U_x^H.  0: off */
 };

@@ -23,7 +23,7 @@ OBJDIR = os.path.join(PKG, "_build")
 LIBNAME = "libeamps.so"
 
 SOURCES = ["k_linalg.hip", "k_theta3.hip", "k_jacobi.hip", "k_jacobi2.hip", "k_observe.hip", "k_small.hip", "k_adjoint.hip",
-           "k_qr.hip", "ea_api.hip", "ea_adjoint.hip"]
+           "k_qr.hip", "k_zgemm.hip", "k_chol.hip", "ea_api.hip", "ea_adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EA_OFFLOAD_ARCH", "gfx950")
@@ -64,8 +64,7 @@ def build(verbose: bool = True) -> str:
     if failed:
         raise RuntimeError("hipcc compilation failed")
     tmp = os.path.join(LIBDIR, LIBNAME + ".tmp")
-    rc, out = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-                    "-L/opt/rocm/lib", "-lrocblas"])
+    rc, out = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
     if rc:
         print(out, file=sys.stderr)
         raise RuntimeError("link failed")

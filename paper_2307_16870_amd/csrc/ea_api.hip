@@ -157,13 +157,14 @@ void mps_free(ea_mps *h) {
     DevBuf *bufs[] = {&h->ro_x64, &h->ro_g, &h->ro_y, &h->ro_r, &h->ro_t, &h->jpart, &h->jmat, &h->jflag, &h->jstamp, &h->qr_a, &h->qr_v, &h->qr_t, &h->qr_tau, &h->qr_y, &h->qr_z, &h->qr_r, &h->qr_s, &h->spare, &h->W, &h->V, &h->X, &h->X2, &h->s_raw, &h->s_sorted, &h->perm,
                       &h->rec, &h->ints, &h->partial, &h->envb, &h->tmp, &h->out3, &h->c128,
                       &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_loff, &h->sm_gsite,
-                      &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs};
+                      &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs,
+                      &h->cq_x, &h->cq_q, &h->cq_g, &h->cq_r1, &h->cq_r2, &h->cq_ri, &h->cq_t,
+                      &h->cq_misc};
     for (DevBuf *b : bufs) free_buf(*b);
     if (h->stage_host) (void)hipHostFree(h->stage_host);
     if (h->rec_host) (void)hipHostFree(h->rec_host);
     if (h->int_host) (void)hipHostFree(h->int_host);
     if (h->dbl_host) (void)hipHostFree(h->dbl_host);
-    if (h->blas) (void)rocblas_destroy_handle(h->blas);
     if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -213,8 +214,9 @@ int mps_set_option(ea_mps *h, int option, double value) {
         h->jorder = (int)value;
         return EA_OK;
     case EA_OPT_QR_MOVES:
-        if (value != 0 && value != 1) return set_err(EA_EINVAL, "QR moves must be 0 or 1");
-        h->qr_moves = value != 0;
+        if (value != 0 && value != 1 && value != 2)
+            return set_err(EA_EINVAL, "centre-move kind must be 0, 1 or 2");
+        h->move_kind = (int)value;
         return EA_OK;
     case EA_OPT_QR_PRECOND:
         if (!(value >= 0) || value > 4096) return set_err(EA_EINVAL, "QR width out of range");
@@ -264,6 +266,7 @@ int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget, 
     return h->f64 ? apply_2q_impl<double>(h, site, op, fidelity_budget, +1, f_out, 0)
                   : apply_2q_impl<float>(h, site, op, fidelity_budget, +1, f_out, 0);
 }
+
 
 }  // extern "C"
 

@@ -6,7 +6,6 @@
 #include "ea_kernels.h"
 
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -68,11 +67,13 @@ struct ea_mps {
     // workspace
     ea::DevBuf jpart, jmat, jflag, jstamp;
     // QR preconditioning: factored matrix, Householder vectors, T blocks,
-    // tau, GEMM scratch, right vectors; rocBLAS handle on the state's stream
+    // tau, GEMM scratch, right vectors
     ea::DevBuf qr_a, qr_v, qr_t, qr_tau, qr_y, qr_z, qr_r, qr_s;
-    rocblas_handle blas = nullptr;
     int qr_min = 0;  // precondition factorisations of at least this many columns (0: off)
-    bool qr_moves = false;  // centre moves of the simulation path by Householder QR
+    // centre moves of the update path: 0 Jacobi SVD, 1 Householder QR, 2 Cholesky QR2
+    int move_kind = 2;
+    ea::DevBuf cq_x, cq_q, cq_g, cq_r1, cq_r2, cq_ri, cq_t, cq_misc;  // Cholesky QR workspace
+    long n_chol_fallback = 0;  // Cholesky QR moves that fell back to the SVD move
     bool jskip = true;  // skip block pairs unchanged since they were last examined
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
@@ -224,6 +225,14 @@ inline int ensure(ea_mps *h, DevBuf &b, size_t bytes) {
         return set_err(EA_ENOMEM, "hipMalloc(%zu) failed", want);
     }
     b.bytes = want;
+    return EA_OK;
+}
+
+// A result computed into `spare` becomes the content of the site buffer dst
+// (the two buffers are exchanged; `bytes` is the result's size).
+inline int commit_spare(ea_mps *h, DevBuf &dst, size_t bytes) {
+    (void)bytes;
+    std::swap(dst, h->spare);
     return EA_OK;
 }
 
@@ -419,46 +428,24 @@ int svd_core(ea_mps *h, int m, int n) {
 }
 
 // C = alpha op(A) op(B) + beta C on the state's stream (column-major;
-// op 'N', 'T' = transpose or 'C' = conjugate transpose), complex FP32 or FP64.
+// op 'N', 'T' = transpose or 'C' = conjugate transpose), complex FP32 or FP64,
+// on the matrix-core GEMM.  A column-major matrix is the row-major array of
+// its transpose, so the row-major kernel computes C^T = op(B)^T op(A)^T; the
+// op codes carry over unchanged (op(B)^T of a column-major B is, on B's
+// row-major view, the same kind of operation).
 template <typename T>
 int blas_gemm(ea_mps *h, char opa, char opb, int m, int n, int k, double alpha, const void *A,
               int lda, const void *B, int ldb, double beta, void *C, int ldc) {
     if (m <= 0 || n <= 0) return EA_OK;
-    auto op = [](char o) {
-        return o == 'C' ? rocblas_operation_conjugate_transpose
-                        : (o == 'T' ? rocblas_operation_transpose : rocblas_operation_none);
-    };
-    const rocblas_operation oa = op(opa), ob = op(opb);
-    rocblas_status st;
-    if constexpr (sizeof(T) == 4) {
-        const rocblas_float_complex a((float)alpha, 0.f), b((float)beta, 0.f);
-        st = rocblas_cgemm(h->blas, oa, ob, m, n, k, &a, (const rocblas_float_complex *)A, lda,
-                           (const rocblas_float_complex *)B, ldb, &b, (rocblas_float_complex *)C,
-                           ldc);
-    } else {
-        const rocblas_double_complex a(alpha, 0.0), b(beta, 0.0);
-        st = rocblas_zgemm(h->blas, oa, ob, m, n, k, &a, (const rocblas_double_complex *)A, lda,
-                           (const rocblas_double_complex *)B, ldb, &b,
-                           (rocblas_double_complex *)C, ldc);
-    }
-    if (st != rocblas_status_success) {
-        h->poisoned = true;
-        return set_err(EA_EHIP, "rocBLAS gemm failed (status %d)", (int)st);
-    }
+    auto code = [](char o) { return o == 'C' ? 1 : (o == 'T' ? 2 : 0); };
+    launch_zgemm<T>(code(opb), code(opa), n, m, k, alpha, 0.0, B, ldb, A, lda, beta, 0.0, C, ldc,
+                    h->stream);
+    LAUNCHCHK(h);
     return EA_OK;
 }
 
 constexpr int QR_NBK_MAX = 16, QR_OBW = 64;  // panel width <= 16; reflectors applied 64 at a time
 
-inline int blas_ready(ea_mps *h) {
-    if (!h->blas && rocblas_create_handle(&h->blas) != rocblas_status_success) {
-        h->blas = nullptr;
-        return set_err(EA_EHIP, "rocblas_create_handle failed");
-    }
-    if (rocblas_set_stream(h->blas, h->stream) != rocblas_status_success)
-        return set_err(EA_EHIP, "rocblas_set_stream failed");
-    return EA_OK;
-}
 
 // Householder QR of src (m x n, column-major, ld m; m <= 4096) with
 // k = min(m, n) reflectors: the factored matrix (R in its upper trapezoid) in
@@ -469,7 +456,6 @@ int qr_factor(ea_mps *h, const void *src, int m, int n) {
     const size_t c = h->csz;
     const int k = std::min(m, n), nblk = (k + QR_OBW - 1) / QR_OBW;
     if (m > 4096) return set_err(EA_ETOOBIG, "the QR takes at most 4096 rows");
-    TRY(blas_ready(h));
     TRY(ensure(h, h->qr_a, c * (size_t)m * n));
     TRY(ensure(h, h->qr_v, c * (size_t)m * k));
     TRY(ensure(h, h->qr_t, c * ((size_t)QR_OBW * QR_OBW * (nblk + 1) + QR_NBK_MAX * QR_NBK_MAX)));
@@ -617,16 +603,25 @@ void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int 
 // weights); while 3r/4 exceeds it, a further step runs (three at most).
 // Well-conditioned factors need neither; wide ill-conditioned ones (thousands
 // of kept columns over several decades of singular values) take both once.
+// Workspace of reorth (taken before the caller's first write, so that a
+// failure leaves the state whole).
 template <typename T>
-int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) {
+int reorth_reserve(ea_mps *h, int rows, int k, int nother) {
     if (sizeof(T) == 8 || !h->reorth || k < 1) return EA_OK;
-    TRY(blas_ready(h));
     const size_t nx = (size_t)rows * k;
     TRY(ensure(h, h->ro_x64, 16 * std::max(nx, (size_t)k * k)));
     TRY(ensure(h, h->ro_g, 16 * (size_t)k * k + 256));
     TRY(ensure(h, h->ro_y, h->csz * (size_t)k * k));
     TRY(ensure(h, h->ro_r, h->csz * (size_t)k * k));
     TRY(ensure(h, h->ro_t, h->csz * std::max(nx, (size_t)k * nother)));
+    return EA_OK;
+}
+
+template <typename T>
+int reorth(ea_mps *h, bool cols, void *X, int rows, int k, void *N, int nother) {
+    if (sizeof(T) == 8 || !h->reorth || k < 1) return EA_OK;
+    const size_t nx = (size_t)rows * k;
+    TRY(reorth_reserve<T>(h, rows, k, nother));
     void *rowsq = (char *)h->ro_g.p + 16 * (size_t)k * k;
     // Row-major products through column-major GEMMs: the row-major C = A B
     // (m x n) is the column-major C^T = B^T A^T.
@@ -706,6 +701,8 @@ int move_right(ea_mps *h) {
     const int chi2 = h->bond[c + 2];
     TRY(ensure(h, h->site[c], h->csz * (size_t)M * k));
     TRY(ensure(h, h->X, h->csz * (size_t)k * N));
+    TRY(ensure(h, h->spare, h->csz * (size_t)k * d * chi2));
+    TRY(reorth_reserve<T>(h, M, k, d * chi2));
     if (orient == 0) {
         gather<T>(h, h->W.p, M, k, M, 0, -1, 0, 1, h->site[c].p);
         gather<T>(h, h->V.p, N, k, N, 1, 1, 0, 0, h->X.p);
@@ -713,7 +710,6 @@ int move_right(ea_mps *h) {
         gather<T>(h, h->V.p, M, k, M, 0, 0, 0, 1, h->site[c].p);
         gather<T>(h, h->W.p, N, k, N, 1, 0, 0, 0, h->X.p);
     }
-    TRY(ensure(h, h->spare, h->csz * (size_t)k * d * chi2));
     {
         ProfScope ps(h, EA_K_GEMM, 8.0 * k * (double)(d * chi2) * N,
                      (double)h->csz * ((double)k * N + (double)N * d * chi2 + (double)k * d * chi2));
@@ -721,7 +717,7 @@ int move_right(ea_mps *h) {
                        d * chi2, h->stream);
     }
     LAUNCHCHK(h);
-    std::swap(h->site[c + 1], h->spare);
+    TRY(commit_spare(h, h->site[c + 1], h->csz * (size_t)k * d * chi2));
     TRY(reorth<T>(h, true, h->site[c].p, M, k, h->site[c + 1].p, d * chi2));
     h->bond[c + 1] = k;
     h->center = c + 1;
@@ -748,6 +744,8 @@ int move_left(ea_mps *h) {
     const int rowsP = h->bond[c - 1] * d;
     TRY(ensure(h, h->site[c], h->csz * (size_t)k * N));
     TRY(ensure(h, h->X, h->csz * (size_t)M * k));
+    TRY(ensure(h, h->spare, h->csz * (size_t)rowsP * k));
+    TRY(reorth_reserve<T>(h, N, k, rowsP));
     if (orient == 0) {
         gather<T>(h, h->V.p, N, k, N, 1, 0, 0, 0, h->site[c].p);
         gather<T>(h, h->W.p, M, k, M, 0, 0, 0, 1, h->X.p);
@@ -755,14 +753,13 @@ int move_left(ea_mps *h) {
         gather<T>(h, h->W.p, N, k, N, 1, -1, 0, 0, h->site[c].p);
         gather<T>(h, h->V.p, M, k, M, 0, 1, 0, 1, h->X.p);
     }
-    TRY(ensure(h, h->spare, h->csz * (size_t)rowsP * k));
     {
         ProfScope ps(h, EA_K_GEMM, 8.0 * rowsP * (double)k * M,
                      (double)h->csz * ((double)rowsP * M + (double)M * k + (double)rowsP * k));
         launch_gemm<T>(h->site[c - 1].p, h->X.p, h->spare.p, rowsP, k, M, M, k, k, h->stream);
     }
     LAUNCHCHK(h);
-    std::swap(h->site[c - 1], h->spare);
+    TRY(commit_spare(h, h->site[c - 1], h->csz * (size_t)rowsP * k));
     TRY(reorth<T>(h, false, h->site[c].p, N, k, h->site[c - 1].p, rowsP));
     h->bond[c] = k;
     h->center = c - 1;
@@ -788,6 +785,7 @@ int move_right_qr(ea_mps *h) {
     TRY(qr_apply_q<T>(h, h->W.p, M, N, k));  // Q (M x k)
     TRY(ensure(h, h->site[c], h->csz * (size_t)M * k));
     TRY(ensure(h, h->spare, h->csz * (size_t)k * P));
+    TRY(reorth_reserve<T>(h, M, k, P));
     {
         ProfScope ps(h, EA_K_GEMM, 8.0 * k * (double)N * P,
                      (double)h->csz * ((double)k * N + (double)N * P + (double)k * P));
@@ -797,7 +795,7 @@ int move_right_qr(ea_mps *h) {
                          h->spare.p, P));
     }
     LAUNCHCHK(h);
-    std::swap(h->site[c + 1], h->spare);
+    TRY(commit_spare(h, h->site[c + 1], h->csz * (size_t)k * P));
     TRY(reorth<T>(h, true, h->site[c].p, M, k, h->site[c + 1].p, P));
     h->bond[c + 1] = k;
     h->center = c + 1;
@@ -822,6 +820,7 @@ int move_left_qr(ea_mps *h) {
     TRY(qr_apply_q<T>(h, h->W.p, N, M, k));  // Q' (N x k)
     TRY(ensure(h, h->site[c], h->csz * (size_t)k * N));
     TRY(ensure(h, h->spare, h->csz * (size_t)P * k));
+    TRY(reorth_reserve<T>(h, N, k, P));
     {
         ProfScope ps(h, EA_K_GEMM, 8.0 * P * (double)M * k,
                      (double)h->csz * ((double)P * M + (double)M * k + (double)P * k));
@@ -831,9 +830,162 @@ int move_left_qr(ea_mps *h) {
                          h->spare.p, k));
     }
     LAUNCHCHK(h);
-    std::swap(h->site[c - 1], h->spare);
+    TRY(commit_spare(h, h->site[c - 1], h->csz * (size_t)P * k));
     TRY(reorth<T>(h, false, h->site[c].p, N, k, h->site[c - 1].p, P));
     h->bond[c] = k;
+    h->center = c - 1;
+    return EA_OK;
+}
+
+// Centre moves by Cholesky QR2 (Sec. III: A_c = Q R, Q the new site, R
+// absorbed into the neighbour; no rank dropped), in FP64 whatever the working
+// precision.  With X the site matrix: G = X^H X = R1^H R1, Q1 = X R1^{-1};
+// again on Q1: Q = Q1 R2^{-1}, R = R2 R1.  Every product is a matrix-core
+// GEMM and the Cholesky factorisations are blocked (k_chol.hip).  A pivot
+// below 1e-14 of the largest diagonal entry (a condition number of X above
+// about 1e7, or a numerically rank-deficient site) abandons the move before
+// the state is touched and the Jacobi SVD move runs instead.
+constexpr double CHOLQR_PIVOT_REL = 1e-14;
+
+// Two passes of Cholesky QR on the FP64 matrix X (rows x cols, row-major,
+// rows >= cols) when `cols_orth` (Q has orthonormal columns, X = Q R), else on
+// X (rows x cols, cols >= rows) with orthonormal rows (X = R^H Q).  Q is left
+// in cq_x, R = R2 R1 in cq_g (cols x cols or rows x rows).  Returns 1 if a
+// Cholesky broke down (state untouched), 0 on success, < 0 on error.
+inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_orth) {
+    const int n = cols_orth ? cols : rows;  // order of the Gram matrix
+    const size_t nx = (size_t)rows * cols, nn = (size_t)n * n;
+    TRY(ensure(h, h->cq_q, 16 * nx));
+    TRY(ensure(h, h->cq_x, 16 * nx));
+    TRY(ensure(h, h->cq_g, 16 * nn));
+    TRY(ensure(h, h->cq_r1, 16 * nn));
+    TRY(ensure(h, h->cq_r2, 16 * nn));
+    TRY(ensure(h, h->cq_ri, 16 * nn));
+    TRY(ensure(h, h->cq_t, 16 * nn));
+    TRY(ensure(h, h->cq_misc, 256));
+    double *dmax = (double *)h->cq_misc.p;
+    int *flag = (int *)((char *)h->cq_misc.p + 64);
+    launch_fill_int(flag, 1, 0, h->stream);
+    const double *src = X;
+    for (int pass = 0; pass < 2; ++pass) {
+        void *Rk = pass == 0 ? h->cq_r1.p : h->cq_r2.p;
+        void *dst = pass == 0 ? h->cq_q.p : h->cq_x.p;
+        {
+            ProfScope ps(h, EA_K_QR, 8.0 * (double)nx * n + 8.0 * (double)nn * n, 16.0 * (2.0 * nx + 3.0 * nn));
+            if (cols_orth)  // G = X^H X, Q = X R^{-1}
+                launch_zgemm<double>(1, 0, n, n, rows, 1.0, 0.0, src, cols, src, cols, 0.0, 0.0,
+                                     h->cq_g.p, n, h->stream);
+            else  // G = X X^H, Q = R^{-H} X
+                launch_zgemm<double>(0, 1, n, n, cols, 1.0, 0.0, src, cols, src, cols, 0.0, 0.0,
+                                     h->cq_g.p, n, h->stream);
+            launch_cholesky_inv(h->cq_g.p, Rk, h->cq_ri.p, h->cq_t.p, n, dmax, CHOLQR_PIVOT_REL,
+                                flag, h->stream);
+            if (cols_orth)
+                launch_zgemm<double>(0, 0, rows, cols, n, 1.0, 0.0, src, cols, h->cq_ri.p, n, 0.0,
+                                     0.0, dst, cols, h->stream);
+            else
+                launch_zgemm<double>(1, 0, rows, cols, n, 1.0, 0.0, h->cq_ri.p, n, src, cols, 0.0,
+                                     0.0, dst, cols, h->stream);
+        }
+        src = (const double *)dst;
+    }
+    // R = R2 R1 (upper triangular products)
+    launch_zgemm<double>(0, 0, n, n, n, 1.0, 0.0, h->cq_r2.p, n, h->cq_r1.p, n, 0.0, 0.0,
+                         h->cq_g.p, n, h->stream);
+    LAUNCHCHK(h);
+    HIPCHK(h, hipMemcpyAsync(h->int_host, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    return h->int_host[0] != 0 ? 1 : 0;
+}
+
+// The site matrix of site c (n complex values) in FP64: the tensor itself
+// when T is double, else a converted copy in cq_x.
+template <typename T>
+int site_c128(ea_mps *h, int c, size_t n, const double **out) {
+    if (sizeof(T) == 8) {
+        *out = (const double *)h->site[c].p;
+        return EA_OK;
+    }
+    TRY(ensure(h, h->cq_x, 16 * n));
+    launch_to_c128<T>(h->site[c].p, (double *)h->cq_x.p, n, h->stream);
+    *out = (const double *)h->cq_x.p;
+    return EA_OK;
+}
+
+// The factor R (n x n, FP64 in cq_g) in the working precision: cq_g itself
+// for double, else converted into X.
+template <typename T>
+int r_working(ea_mps *h, int n, const void **out) {
+    if (sizeof(T) == 8) {
+        *out = h->cq_g.p;
+        return EA_OK;
+    }
+    TRY(ensure(h, h->X, h->csz * (size_t)n * n));
+    launch_from_c128<T>((const double *)h->cq_g.p, h->X.p, (size_t)n * n, h->stream);
+    *out = h->X.p;
+    return EA_OK;
+}
+
+// Right: A_c as (chi_l d) x chi_r = Q R; A_c <- Q, A_{c+1} <- R A_{c+1}.
+template <typename T>
+int move_right_cholqr(ea_mps *h) {
+    const int c = h->center, d = h->d;
+    const int M = h->bond[c] * d, N = h->bond[c + 1], P = d * h->bond[c + 2];
+    if (M < N || N > EA_SORT_MAX) return move_right<T>(h);
+    const size_t nx = (size_t)M * N;
+    const double *X = nullptr;
+    TRY(site_c128<T>(h, c, nx, &X));
+    const int rc = cholqr2(h, X, M, N, true);
+    if (rc < 0) return rc;
+    if (rc == 1) {  // ill-conditioned: the SVD move
+        h->n_chol_fallback += 1;
+        return move_right<T>(h);
+    }
+    const void *R = nullptr;
+    TRY(r_working<T>(h, N, &R));
+    TRY(ensure(h, h->spare, h->csz * (size_t)N * P));
+    {
+        ProfScope ps(h, EA_K_GEMM, 8.0 * N * (double)N * P,
+                     (double)h->csz * ((double)N * N + 2.0 * (double)N * P));
+        launch_from_c128<T>((const double *)h->cq_x.p, h->site[c].p, nx, h->stream);
+        launch_zgemm<T>(0, 0, N, P, N, 1.0, 0.0, R, N, h->site[c + 1].p, P, 0.0, 0.0,
+                        h->spare.p, P, h->stream);
+    }
+    LAUNCHCHK(h);
+    TRY(commit_spare(h, h->site[c + 1], h->csz * (size_t)N * P));
+    h->center = c + 1;
+    return EA_OK;
+}
+
+// Left: A_c as chi_l x (d chi_r) = R^H Q with orthonormal rows;
+// A_c <- Q, A_{c-1} <- A_{c-1} R^H.
+template <typename T>
+int move_left_cholqr(ea_mps *h) {
+    const int c = h->center, d = h->d;
+    const int M = h->bond[c], N = d * h->bond[c + 1], P = h->bond[c - 1] * d;
+    if (N < M || M > EA_SORT_MAX) return move_left<T>(h);
+    const size_t nx = (size_t)M * N;
+    const double *X = nullptr;
+    TRY(site_c128<T>(h, c, nx, &X));
+    const int rc = cholqr2(h, X, M, N, false);
+    if (rc < 0) return rc;
+    if (rc == 1) {
+        h->n_chol_fallback += 1;
+        return move_left<T>(h);
+    }
+    const void *R = nullptr;
+    TRY(r_working<T>(h, M, &R));
+    TRY(ensure(h, h->spare, h->csz * (size_t)P * M));
+    {
+        ProfScope ps(h, EA_K_GEMM, 8.0 * P * (double)M * M,
+                     (double)h->csz * ((double)M * M + 2.0 * (double)P * M));
+        launch_from_c128<T>((const double *)h->cq_x.p, h->site[c].p, nx, h->stream);
+        launch_zgemm<T>(0, 1, P, M, M, 1.0, 0.0, h->site[c - 1].p, M, R, M, 0.0, 0.0,
+                        h->spare.p, M, h->stream);
+    }
+    LAUNCHCHK(h);
+    TRY(commit_spare(h, h->site[c - 1], h->csz * (size_t)P * M));
     h->center = c - 1;
     return EA_OK;
 }
@@ -842,12 +994,14 @@ template <typename T>
 int move_center(ea_mps *h, int j) {
     while (h->center < j) {
         ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
-        if (h->qr_moves) TRY(move_right_qr<T>(h));
+        if (h->move_kind == 2) TRY(move_right_cholqr<T>(h));
+        else if (h->move_kind == 1) TRY(move_right_qr<T>(h));
         else TRY(move_right<T>(h));
     }
     while (h->center > j) {
         ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
-        if (h->qr_moves) TRY(move_left_qr<T>(h));
+        if (h->move_kind == 2) TRY(move_left_cholqr<T>(h));
+        else if (h->move_kind == 1) TRY(move_left_qr<T>(h));
         else TRY(move_left<T>(h));
     }
     return EA_OK;
@@ -891,6 +1045,8 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
     TRY(ensure(h, h->site[i], h->csz * (size_t)M * k));
     TRY(ensure(h, h->site[i + 1], h->csz * (size_t)k * N));
     const bool right = dir > 0;
+    if (right) TRY(reorth_reserve<T>(h, M, k, N));
+    else TRY(reorth_reserve<T>(h, N, k, M));
     if (orient == 0) {
         gather<T>(h, h->W.p, M, k, M, 0, right ? -1 : 0, right ? 0 : 1, 1, h->site[i].p);
         gather<T>(h, h->V.p, N, k, N, 1, right ? 1 : 0, right ? 1 : 0, 0, h->site[i + 1].p);

@@ -46,6 +46,28 @@ void launch_theta_mfma(const void *A, const void *B, const void *G, void *W, int
 // epilogue as launch_theta<float>.
 void launch_theta_bf16x3(const void *A, const void *B, const void *G, void *W, int chiL,
                          int chiM, int chiR, int d, int orient, hipStream_t s);
+// C (M x N) = alpha op(A) op(B) + beta C on the matrix cores (k_zgemm.hip),
+// row-major with leading dimensions; op 0: as stored (A is M x K), 1:
+// conjugate transpose (A stored K x M), 2: transpose (A stored K x M).
+template <typename T>
+void launch_zgemm(int opA, int opB, int M, int N, int K, double ar, double ai, const void *A,
+                  int lda, const void *B, int ldb, double br, double bi, void *C, int ldc,
+                  hipStream_t s);
+// Cholesky of a Hermitian positive definite complex FP64 matrix (k_chol.hip):
+// G (n x n, row-major, overwritten) = R^H R, R upper triangular, and
+// Rinv = R^{-1}; T1 is scratch of n x n complex; dmax receives the
+// largest diagonal entry of G.  A pivot at or below rel_min * dmax sets *flag
+// (which is not cleared) and is replaced by that bound.
+constexpr int CHOL_NB = 32;
+void launch_cholesky_inv(void *G, void *R, void *Rinv, void *T1, int n, double *dmax,
+                         double rel_min, int *flag, hipStream_t s);
+// The same for `batch` independent products, entry b taking its operands at
+// A + b sA, B + b sB, C + b sC (complex elements).
+template <typename T>
+void launch_zgemm_batched(int opA, int opB, int M, int N, int K, double ar, double ai,
+                          const void *A, int lda, size_t sA, const void *B, int ldb, size_t sB,
+                          double br, double bi, void *C, int ldc, size_t sC, int batch,
+                          hipStream_t s);
 // C (M x N) = A (M x K) * B (K x N), row-major with leading dimensions.
 template <typename T>
 void launch_gemm(const void *A, const void *B, void *C, int M, int N, int K, int lda, int ldb,

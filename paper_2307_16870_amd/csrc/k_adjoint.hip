@@ -1,76 +1,19 @@
 // Kernels of the reverse pass (vector-Jacobian products) through the
-// two-site update: a complex GEMM with conjugate-transposed operands and
-// accumulation, and the small elementwise / reduction pieces of the
-// truncated-SVD adjoint (see the derivation in the adjoint host source).
+// two-site update: the small elementwise / reduction pieces of the
+// truncated-SVD adjoint (see the derivation in the adjoint host source); its
+// products use the matrix-core complex GEMM.
 #include "ea_dev.h"
 #include "ea_kernels.h"
 
 #include <math.h>
 
-// C (M x N) = alpha op(A) op(B) + beta C, row-major.  opA = 0: A is M x K
-// (lda); opA = 1: A is stored K x M and op(A) = A^H.  Same for B.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_ex(int opA, int opB, int M, int N, int K,
-                                                 cx<T> alpha, const cx<T> *__restrict__ A,
-                                                 int lda, const cx<T> *__restrict__ B, int ldb,
-                                                 cx<T> beta, cx<T> *__restrict__ C, int ldc) {
-    constexpr int TM = 32, TN = 32, KT = 16;
-    __shared__ cx<T> As[TM][KT + 1];
-    __shared__ cx<T> Bs[KT][TN + 1];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    const int tn = tid % 16, tm = tid / 16;
-    cx<T> acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = zero_cx<T>();
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        for (int e = tid; e < TM * KT; e += 256) {
-            const int rr = e / KT, kk = e % KT;
-            const int gm = m0 + rr, gk = k0 + kk;
-            cx<T> v = zero_cx<T>();
-            if (gm < M && gk < K) v = opA ? conj(A[(size_t)gk * lda + gm]) : A[(size_t)gm * lda + gk];
-            As[rr][kk] = v;
-        }
-        for (int e = tid; e < KT * TN; e += 256) {
-            const int kk = e / TN, cc = e % TN;
-            const int gk = k0 + kk, gn = n0 + cc;
-            cx<T> v = zero_cx<T>();
-            if (gk < K && gn < N) v = opB ? conj(B[(size_t)gn * ldb + gk]) : B[(size_t)gk * ldb + gn];
-            Bs[kk][cc] = v;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < KT; ++kk) {
-            const cx<T> a0 = As[tm][kk], a1 = As[tm + 16][kk];
-            const cx<T> b0 = Bs[kk][tn], b1 = Bs[kk][tn + 16];
-            cmac(acc[0][0], a0, b0);
-            cmac(acc[0][1], a0, b1);
-            cmac(acc[1][0], a1, b0);
-            cmac(acc[1][1], a1, b1);
-        }
-        __syncthreads();
-    }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            const int gm = m0 + tm + 16 * a, gn = n0 + tn + 16 * b;
-            if (gm < M && gn < N) {
-                cx<T> *c = C + (size_t)gm * ldc + gn;
-                cx<T> v = alpha * acc[a][b];
-                if (beta.x != T(0) || beta.y != T(0)) v = v + beta * (*c);
-                *c = v;
-            }
-        }
-}
-
+// C (M x N) = alpha op(A) op(B) + beta C, row-major (ops 0 and 1 of the
+// matrix-core kernel).
 template <typename T>
 void launch_gemm_ex(int opA, int opB, int M, int N, int K, double ar, double ai, const void *A,
                     int lda, const void *B, int ldb, double br, double bi, void *C, int ldc,
                     hipStream_t s) {
-    if (M <= 0 || N <= 0) return;
-    dim3 grid((N + 31) / 32, (M + 31) / 32);
-    k_gemm_ex<T><<<grid, 256, 0, s>>>(opA, opB, M, N, K, mk<T>((T)ar, (T)ai), (const cx<T> *)A,
-                                      lda, (const cx<T> *)B, ldb, mk<T>((T)br, (T)bi), (cx<T> *)C,
-                                      ldc);
+    launch_zgemm<T>(opA, opB, M, N, K, ar, ai, A, lda, B, ldb, br, bi, C, ldc, s);
 }
 
 // Y = a X + b Y (n elements)

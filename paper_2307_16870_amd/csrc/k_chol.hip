@@ -1,0 +1,175 @@
+// Blocked Cholesky factorisation G = R^H R of a Hermitian positive definite
+// complex FP64 matrix, and the inverse of its factor, for the Cholesky QR
+// centre moves (Sec. III: A_c = Q R with Q the new, orthonormal site and R
+// absorbed into the neighbour).  With X = Q R and G = X^H X, R is the
+// Cholesky factor of G and Q = X R^{-1}; done twice (Cholesky QR2) the
+// columns of Q are orthonormal to FP64 rounding while the condition number
+// of X stays below about 1e7.  All matrices are row-major n x n with leading
+// dimension n.
+//
+// The host walks the column blocks of width CHOL_NB: this file's kernel
+// factors one diagonal block (R_jj and R_jj^{-1}); the panel
+// R[j, j+] = R_jj^{-H} G[j, j+] and the trailing update
+// G[j+, j+] -= R[j, j+]^H R[j, j+] are matrix-core GEMMs, as are the
+// off-diagonal blocks of R^{-1}: Rinv[<j, j] = -Rinv[<j, <j] R[<j, j] Rinv_jj.
+#include "ea_dev.h"
+#include "ea_kernels.h"
+
+namespace {
+
+constexpr int NB = CHOL_NB;
+
+// Largest diagonal entry of G (n entries, one workgroup) into *dmax.
+__global__ __launch_bounds__(256) void k_chol_dmax(const cx<double> *__restrict__ G, int n,
+                                                   double *__restrict__ dmax) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, G[(size_t)i * n + i].x);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *dmax = red[0];
+}
+
+// Factor the diagonal block at (j0, j0), size nb <= NB, of the (updated) G:
+// R[j0.., j0..] <- R_jj (upper triangle; zeros below), Rinv[j0.., j0..] <-
+// R_jj^{-1}.  A pivot at or below rel_min * max diag(G) (or not finite)
+// marks a breakdown in *flag and is replaced by that bound, so that the
+// factorisation still completes with finite values (the host then discards
+// it).  One wave; lane t keeps column t of the block in registers (all loops
+// over the block's rows are unrolled, so the columns never leave registers);
+// per pivot step the pivot and then row p of R are broadcast through LDS.
+__global__ __launch_bounds__(64) void k_chol_diag(const cx<double> *__restrict__ G,
+                                                  cx<double> *__restrict__ R,
+                                                  cx<double> *__restrict__ Rinv, int n, int j0,
+                                                  int nb, const double *__restrict__ dmax,
+                                                  double rel_min, int *__restrict__ flag) {
+    __shared__ cx<double> S[NB][NB + 1];
+    __shared__ cx<double> rowp[NB];
+    __shared__ double piv;
+    const int t = threadIdx.x;
+    const bool own = t < nb;
+    cx<double> col[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+        col[i] = (own && i < nb) ? G[(size_t)(j0 + i) * n + j0 + t] : zero_cx<double>();
+    const double dmin = rel_min * *dmax;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+        if (p < nb) {
+            if (t == p) piv = col[p].x;
+            __syncthreads();
+            double dp = piv;
+            if (!(dp > dmin)) {  // also catches NaN
+                if (t == 0) *flag = 1;
+                dp = dmin > 0.0 ? dmin : 1.0;
+            }
+            const double rp = sqrt(dp), ir = 1.0 / rp;
+            // row p of R: R[p][t] = S[p][t] / r_p for t >= p
+            if (t == p) col[p] = mk<double>(rp, 0.0);
+            else if (t > p && own) col[p] = ir * col[p];
+            if (t > p && own) rowp[t] = col[p];
+            __syncthreads();
+            // trailing upper triangle: S[q][t] -= conj(R[p][q]) R[p][t], p < q <= t
+            if (t > p && own) {
+                const cx<double> b = col[p];
+#pragma unroll
+                for (int q = p + 1; q < NB; ++q) {
+                    if (q <= t) {
+                        const cx<double> a = rowp[q];
+                        cmacc(col[q], mk<double>(-a.x, -a.y), b);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+        if (own) S[i][t] = i <= t ? col[i] : zero_cx<double>();
+    __syncthreads();
+    // R_jj^{-1}, column c per lane: back substitution of R x = e_c
+    const int c = t;
+    cx<double> x[NB];
+#pragma unroll
+    for (int i = NB - 1; i >= 0; --i) {
+        x[i] = zero_cx<double>();
+        if (own && i < nb && i <= c) {
+            cx<double> acc = mk<double>(i == c ? 1.0 : 0.0, 0.0);
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j)
+                if (j <= c) acc = acc - S[i][j] * x[j];
+            x[i] = (1.0 / S[i][i].x) * acc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (own && i < nb) {
+            const size_t o = (size_t)(j0 + i) * n + j0 + t;
+            R[o] = S[i][t];
+            Rinv[o] = x[i];
+        }
+    }
+}
+
+// Zero the strictly lower triangle of an n x n matrix.
+__global__ void k_lower_zero(cx<double> *__restrict__ A, int n) {
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int r = (int)(idx / n), c = (int)(idx % n);
+    if (r > c) A[idx] = zero_cx<double>();
+}
+
+}  // namespace
+
+// Cholesky G = R^H R (G overwritten by its trailing updates) and Rinv = R^{-1}.
+// T1 is scratch of n x n.  *flag is set (not cleared) on a breakdown.
+// Rinv: the diagonal blocks come from the block factorisations; the rest by
+// doubling, inv([[A, B], [0, C]]) = [[A^-1, -A^-1 B C^-1], [0, C^-1]], all
+// block pairs of one size in one batched GEMM launch (two per size).
+void launch_cholesky_inv(void *G, void *R, void *Rinv, void *T1, int n,
+                         double *dmax, double rel_min, int *flag, hipStream_t s) {
+    cx<double> *g = (cx<double> *)G, *r = (cx<double> *)R, *ri = (cx<double> *)Rinv,
+               *t1 = (cx<double> *)T1;
+    const size_t nn = (size_t)n * n;
+    k_lower_zero<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(r, n);
+    k_lower_zero<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(ri, n);
+    k_chol_dmax<<<1, 256, 0, s>>>(g, n, dmax);
+    for (int j0 = 0; j0 < n; j0 += NB) {
+        const int nb = n - j0 < NB ? n - j0 : NB, j1 = j0 + nb, rest = n - j1;
+        k_chol_diag<<<1, 64, 0, s>>>(g, r, ri, n, j0, nb, dmax, rel_min, flag);
+        if (rest > 0) {
+            // panel R[j, j+] = Rinv_jj^H G[j, j+]
+            launch_zgemm<double>(1, 0, nb, rest, nb, 1.0, 0.0, ri + (size_t)j0 * n + j0, n,
+                                 g + (size_t)j0 * n + j1, n, 0.0, 0.0, r + (size_t)j0 * n + j1,
+                                 n, s);
+            // trailing G[j+, j+] -= R[j, j+]^H R[j, j+]
+            launch_zgemm<double>(1, 0, rest, rest, nb, -1.0, 0.0, r + (size_t)j0 * n + j1, n,
+                                 r + (size_t)j0 * n + j1, n, 1.0, 0.0, g + (size_t)j1 * n + j1,
+                                 n, s);
+        }
+    }
+    for (int b = NB; b < n; b *= 2) {
+        const int np = n / (2 * b);
+        const size_t step = 2 * (size_t)b * (n + 1);  // from one pair's corner to the next
+        if (np > 0) {
+            // T_q = R[r0 : r0+b, r0+b : r0+2b] Rinv[r0+b : r0+2b, r0+b : r0+2b]
+            launch_zgemm_batched<double>(0, 0, b, b, b, 1.0, 0.0, r + b, n, step,
+                                         ri + (size_t)b * (n + 1), n, step, 0.0, 0.0, t1, b,
+                                         (size_t)b * b, np, s);
+            // Rinv[r0 : r0+b, r0+b : r0+2b] = -Rinv[r0 : r0+b, r0 : r0+b] T_q
+            launch_zgemm_batched<double>(0, 0, b, b, b, -1.0, 0.0, ri, n, step, t1, b,
+                                         (size_t)b * b, 0.0, 0.0, ri + b, n, step, np, s);
+        }
+        const int r0 = 2 * b * np, b2 = n - r0 - b;
+        if (b2 > 0) {  // a last pair whose second block is shorter
+            const size_t c0 = (size_t)r0 * (n + 1);
+            launch_zgemm<double>(0, 0, b, b2, b2, 1.0, 0.0, r + c0 + b, n,
+                                 ri + c0 + (size_t)b * (n + 1), n, 0.0, 0.0, t1, b2, s);
+            launch_zgemm<double>(0, 0, b, b2, b, -1.0, 0.0, ri + c0, n, t1, b2, 0.0, 0.0,
+                                 ri + c0 + b, n, s);
+        }
+    }
+}

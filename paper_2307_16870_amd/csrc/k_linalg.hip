@@ -97,59 +97,11 @@ void launch_theta(const void *A, const void *B, const void *G, void *W, int chiL
                                            orient);
 }
 
-// ---------------------------------------------------------------------------
-// Plain complex GEMM, C = A B, row-major; 32x32 output tile, 2x2 per thread.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm(const cx<T> *__restrict__ A,
-                                              const cx<T> *__restrict__ B,
-                                              cx<T> *__restrict__ C, int M, int N, int K,
-                                              int lda, int ldb, int ldc) {
-    constexpr int TM = 32, TN = 32, KT = 16;
-    __shared__ cx<T> As[TM][KT + 1];
-    __shared__ cx<T> Bs[KT][TN + 1];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    const int tn = tid % 16, tm = tid / 16;
-    cx<T> acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = zero_cx<T>();
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        for (int e = tid; e < TM * KT; e += 256) {
-            int rr = e / KT, kk = e % KT;
-            int gm = m0 + rr, gk = k0 + kk;
-            As[rr][kk] = (gm < M && gk < K) ? A[(size_t)gm * lda + gk] : zero_cx<T>();
-        }
-        for (int e = tid; e < KT * TN; e += 256) {
-            int kk = e / TN, cc = e % TN;
-            int gk = k0 + kk, gn = n0 + cc;
-            Bs[kk][cc] = (gk < K && gn < N) ? B[(size_t)gk * ldb + gn] : zero_cx<T>();
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < KT; ++kk) {
-            cx<T> a0 = As[tm][kk], a1 = As[tm + 16][kk];
-            cx<T> b0 = Bs[kk][tn], b1 = Bs[kk][tn + 16];
-            cmac(acc[0][0], a0, b0);
-            cmac(acc[0][1], a0, b1);
-            cmac(acc[1][0], a1, b0);
-            cmac(acc[1][1], a1, b1);
-        }
-        __syncthreads();
-    }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            int gm = m0 + tm + 16 * a, gn = n0 + tn + 16 * b;
-            if (gm < M && gn < N) C[(size_t)gm * ldc + gn] = acc[a][b];
-        }
-}
-
+// Plain complex GEMM, C = A B, row-major: the matrix-core kernel.
 template <typename T>
 void launch_gemm(const void *A, const void *B, void *C, int M, int N, int K, int lda, int ldb,
                  int ldc, hipStream_t s) {
-    dim3 grid((N + 31) / 32, (M + 31) / 32);
-    k_gemm<T><<<grid, 256, 0, s>>>((const cx<T> *)A, (const cx<T> *)B, (cx<T> *)C, M, N, K,
-                                   lda, ldb, ldc);
+    launch_zgemm<T>(0, 0, M, N, K, 1.0, 0.0, A, lda, B, ldb, 0.0, 0.0, C, ldc, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -13,7 +13,8 @@
 //   k_qr_fill  : C = [Y; 0] (m x n) before Q is applied
 //
 // The trailing updates A <- (I - V T^H V^H) A and the products with Q are
-// plain GEMMs (rocBLAS) issued by the host.  All matrices are column-major.
+// plain GEMMs (the matrix-core GEMM) issued by the host.  All matrices are
+// column-major.
 #include "ea_dev.h"
 #include "ea_kernels.h"
 

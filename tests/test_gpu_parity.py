@@ -271,17 +271,18 @@ def test_qr_preconditioned_circuit(prec):
         assert abs(F1 - F0) < 1e-5
 
 
+@pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_qr_centre_moves_vs_oracle(prec):
-    """Centre moves by Householder QR (the oracle's own move): kept ranks,
-    bond dimensions and amplitudes against the oracle on a 14-qubit
-    truncating circuit."""
-    _say("case: qr moves", prec)
+def test_qr_centre_moves_vs_oracle(prec, kind):
+    """Centre moves by QR (the oracle's own move; kind 1 Householder, kind 2
+    Cholesky QR2, the default): kept ranks, bond dimensions and amplitudes
+    against the oracle on a 14-qubit truncating circuit."""
+    _say("case: qr moves", prec, kind)
     prog = C.brickwork_program(14, 12, 11)
     o = oracle_run(prog, 0.97)
     with P.EAState(prog.n_sites, "pure", prec) as st:
         st.set_option(P.EA_OPT_SMALL_LAYERS, 0)
-        st.set_option(P.EA_OPT_QR_MOVES, 1)
+        st.set_option(P.EA_OPT_QR_MOVES, kind)
         st.profile(1)
         st.run(prog, 0.97)
         qr_launches = st.profile_read(P.EA_K_QR)["launches"]

@@ -198,16 +198,20 @@ def test_noisy_fig2b_lower_fmin_truncates_more():
     assert tot[0] > tot[1]
 
 
-@pytest.mark.parametrize("prec", ["c64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["c128", "c64", "bf16x3"])
 def test_mpo_circuit_reduced_precision_vs_oracle(prec):
-    """Mixed-state circuit in reduced precision (complex FP32 contraction and
-    Jacobi, or BF16x3 contraction; FP64 fidelity product): 8 qubits, depth 8,
-    Haar gates fused with two-qubit depolarising p = 1e-2, F_min = 0.95.
-    P, <Z_i> and <Z_i Z_{i+1}> within 1e-4 of the FP64 oracle; protected kept
-    ranks equal (margin 1e-6 T)."""
+    """Mixed-state circuit (FP64, or reduced precision: complex FP32
+    contraction and Jacobi, or BF16x3 contraction; FP64 fidelity product):
+    8 qubits, depth 8, Haar gates fused with two-qubit depolarising p = 1e-2,
+    F_min = 0.95.  P, <Z_i> and <Z_i Z_{i+1}> within 1e-4 of the FP64 oracle
+    (1e-10 in FP64); protected kept ranks equal (margin 1e-6 T).  The seed is
+    one whose every cut falls between distinct singular values (gap above
+    5e-4 s_0): where the last kept and the first dropped value are equal the
+    kept vectors are not unique, and the two runs may legitimately keep
+    different ones (seed 33 of this family has such a cut)."""
     _say("case: mpo reduced precision", prec)
     n = 8
-    prog = C.brickwork_program(n, 8, 33, kind="mixed", noise_p=1e-2)
+    prog = C.brickwork_program(n, 8, 30, kind="mixed", noise_p=1e-2)
     with P.EAState(n, "mixed", prec) as st:
         st.run(prog, 0.95)
         glog = st.gate_log()
@@ -215,6 +219,8 @@ def test_mpo_circuit_reduced_precision_vs_oracle(prec):
         ev = st.expect(list(range(n)) + list(range(n - 1)), [1] * n + [2] * (n - 1),
                        [Z] * n + [np.kron(Z, Z)] * (n - 1))
     o = oracle_run(prog, 0.95)
+    gaps = [(r.s[r.k - 1] - r.s[r.k]) / r.s[0] for r in o.log if r.k < len(r.s)]
+    assert min(gaps) > 5e-4
     ref = [o.expect(i, 1, Z) for i in range(n)] + [o.expect(i, 2, np.kron(Z, Z)) for i in range(n - 1)]
     n_prot = 0
     for g, r in zip(glog, o.log):
@@ -226,8 +232,9 @@ def test_mpo_circuit_reduced_precision_vs_oracle(prec):
     df = max(abs(g["f"] - r.f) for g, r in zip(glog, o.log))
     _say(f"error table mpo8 [{prec}]: protected ranks {n_prot}/{len(glog)} equal, "
          f"max |df| {df:.2e}, |dP| {dP:.2e}, max |d<O>| {dO:.2e}")
-    assert dP < 1e-4
-    assert dO < 1e-4
+    tol = 1e-10 if prec == "c128" else 1e-4
+    assert dP < tol
+    assert dO < tol
 
 
 def test_forced_rank_replay_vs_oracle():
@@ -239,15 +246,25 @@ def test_forced_rank_replay_vs_oracle():
     n = 12
     prog = C.brickwork_program(n, 10, 64)
     probe = oracle_run(prog, 0.95)
-    ranks = [max(1, r.k - 1) if j % 3 == 0 else r.k for j, r in enumerate(probe.log)]
+    wanted = [max(1, r.k - 1) if j % 3 == 0 else r.k for j, r in enumerate(probe.log)]
+    # the forced run's bonds differ from the probe's, so each rank is capped
+    # by the number of singular values of that run's two-site matrix (as the
+    # library caps it)
     o = OracleMPS(n, "pure", keep_spectra=True)
     o.set_schedule(0.95, prog.n_2q)
-    it = iter(ranks)
+    it = iter(wanted)
+    ranks = []
     for layer in prog.layers:
         sites = [op.site for op in layer]
         asc = abs(o.center - min(sites)) <= abs(o.center - max(sites))
         for op in sorted(layer, key=lambda q: q.site, reverse=not asc):
-            o.apply_2q(op.site, op.mat, None, "right" if asc else "left", forced_k=next(it))
+            i = op.site
+            if not (o.center == i or o.center == i + 1):
+                o.move_center(i if o.center < i else i + 1)
+            r = min(o.d * o.A[i].shape[0], o.d * o.A[i + 1].shape[2])
+            ranks.append(min(next(it), r))
+            o.apply_2q(i, op.mat, None, "right" if asc else "left", forced_k=ranks[-1])
+    assert ranks != [r.k for r in probe.log]  # forced away from the rule
     with P.EAState(n, "pure", "c128") as st:
         st.replay(prog, ranks, 0.95)
         glog = st.gate_log()
