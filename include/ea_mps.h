@@ -138,6 +138,10 @@ enum ea_option {
                                 no rank dropped.  0: the Jacobi SVD, dropping numerically
                                 zero singular values.  The gradient path (mps_energy_grad)
                                 always moves by SVD. */
+    EA_OPT_RESERVE_BOND = 14,/* chi > 0: grow every site tensor's buffer now to hold a
+                                (chi, d, chi) tensor (never shrunk), so that later updates up
+                                to bond chi need no new site memory, as the allocation-free
+                                entry point requires.  Allocates; EA_ENOMEM on failure. */
     EA_OPT_QR_PRECOND = 12   /* w > 0: a factorisation of at least w columns on the
                                 three-kernel Jacobi first takes the Householder QR of its
                                 matrix (Theta = Q R, panels on one workgroup each, trailing
@@ -273,6 +277,35 @@ int mps_apply_1q(ea_mps *h, int site, const double *op);
  *  The centre ends on site+1.  Returns EA_WARN_CAPPED if chi_max bound. */
 int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget,
                  double *f_out);
+
+/* Size of the device array that holds the workspace of mps_apply_2q_noalloc:
+ * one per GPU the library runs on, held until the process ends. */
+#define EA_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* mps_apply_2q without any device allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, update, result and
+ * warnings as mps_apply_2q, except:
+ *  - no device memory is allocated or freed (no hipMalloc / hipFree, no
+ *    allocator callback, no library routine that allocates): the update's
+ *    workspace (two-site matrix, Jacobi buffers, centre-move and FP64
+ *    re-orthogonalisation buffers) is carved from one library-owned device
+ *    array of EA_NOALLOC_SCRATCH_BYTES per GPU, and every site tensor's
+ *    buffer must already hold its result (grown by earlier updates, or
+ *    reserved with EA_OPT_RESERVE_BOND);
+ *  - EA_ETOOBIG when the workspace would exceed the array (about bond 1024 for
+ *    a pure state in complex FP32 or FP64) or a site buffer is too small; the
+ *    state is then unchanged except that the orthogonality centre may have
+ *    moved (an exact re-gauging of the same state);
+ *  - all calls on one GPU share the array, which keeps the last call's
+ *    contents (nothing in it is assumed to start at zero): calls that overlap
+ *    on one GPU race (other threads, or another stream before this call's
+ *    work has finished); calls on one stream are ordered;
+ *  - the calling thread's current device must be the handle's (EA_EINVAL);
+ *  - event timing (mps_profile) is suspended for the call.
+ * The host-side gate log still grows by one record. */
+int mps_apply_2q_noalloc(ea_mps *h, int site, const double *op, double fidelity_budget,
+                         double *f_out);
 
 /* A layer of two-site updates on disjoint pairs (sites[j], sites[j]+1): the
  * update of Sec. V-VI applied to each gate of one circuit layer.  The paper

@@ -25,7 +25,8 @@ EA_NAIVE, EA_GLOBAL, EA_NEAREST, EA_FIXED = 0, 1, 2, 3
 EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
 EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL, EA_OPT_ROT_THREADS, EA_OPT_REORTH = 5, 6, 7, 8
 EA_OPT_JACOBI_ORDER, EA_OPT_SMALL_LAYERS, EA_OPT_JACOBI_SKIP, EA_OPT_QR_PRECOND = 9, 10, 11, 12
-EA_OPT_QR_MOVES = 13
+EA_OPT_QR_MOVES, EA_OPT_RESERVE_BOND = 13, 14
+EA_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 SYMBOLS = [
     "mps_init_product", "mps_free", "mps_set_option", "mps_set_schedule", "mps_apply_1q",
@@ -34,7 +35,7 @@ SYMBOLS = [
     "mps_get_site", "mps_reset_product", "mps_profile", "mps_profile_read",
     "mps_apply_layer_batched", "mps_run_layers_batched", "mps_energy_grad", "ea_last_error",
     "mps_set_tuning", "mps_get_tuning", "mps_program_capture", "mps_program_launch",
-    "mps_program_free", "mps_apply_layer_ranks",
+    "mps_program_free", "mps_apply_layer_ranks", "mps_apply_2q_noalloc",
 ]
 
 # Lorentzian broadening of the SVD adjoint's 1/(s_j^2 - s_i^2) factors,
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ct.CDLL:
         "mps_set_schedule": (I, [P, D, L, I]),
         "mps_apply_1q": (I, [P, I, dp]),
         "mps_apply_2q": (I, [P, I, dp, D, dp]),
+        "mps_apply_2q_noalloc": (I, [P, I, dp, D, dp]),
         "mps_apply_layer": (I, [P, I, ip, dp, dp, dp]),
         "mps_apply_layer_ranks": (I, [P, I, ip, dp, ip, dp]),
         "mps_fidelity_estimate": (I, [P, dp, dp]),
@@ -240,6 +242,16 @@ def mps_apply_2q(h, site, op, fidelity_budget=-1.0):
     o = _c(op)
     f = ct.c_double(0.0)
     rc = _chk(_lib.mps_apply_2q(h, int(site), _dp(o), float(fidelity_budget), ct.byref(f)))
+    return rc, f.value
+
+
+def mps_apply_2q_noalloc(h, site, op, fidelity_budget=-1.0):
+    """mps_apply_2q with its workspace in the library's fixed device array
+    (no device allocation).  Returns (status, achieved f)."""
+    o = _c(op)
+    f = ct.c_double(0.0)
+    rc = _chk(_lib.mps_apply_2q_noalloc(h, int(site), _dp(o), float(fidelity_budget),
+                                        ct.byref(f)))
     return rc, f.value
 
 

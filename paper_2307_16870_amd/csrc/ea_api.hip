@@ -81,6 +81,11 @@ int mps_init_product(int n_sites, int kind, int prec, int chi_max, const double 
         return set_err(EA_EINVAL, "allocator needs both alloc and free");
     ea_mps *h = new ea_mps();
     if (alloc) h->alloc = *alloc;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return set_err(EA_EHIP, "hipGetDevice failed");
+    }
     h->n = n_sites;
     h->d = d;
     h->kind = kind;
@@ -218,6 +223,23 @@ int mps_set_option(ea_mps *h, int option, double value) {
             return set_err(EA_EINVAL, "centre-move kind must be 0, 1 or 2");
         h->move_kind = (int)value;
         return EA_OK;
+    case EA_OPT_RESERVE_BOND: {
+        if (!(value >= 1) || value > 65536) return set_err(EA_EINVAL, "reserve bond out of range");
+        const size_t chi = (size_t)value, want = h->csz * chi * h->d * chi;
+        for (int i = 0; i < h->n; ++i) {
+            if (h->site[i].bytes >= want) continue;
+            // a larger buffer holding the current tensor
+            DevBuf nb;
+            TRY(ensure(h, nb, want));
+            const size_t used = h->csz * (size_t)h->bond[i] * h->d * h->bond[i + 1];
+            HIPCHK(h, hipMemcpyAsync(nb.p, h->site[i].p, used, hipMemcpyDeviceToDevice,
+                                     h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            free_buf(h->site[i]);
+            h->site[i] = nb;
+        }
+        return EA_OK;
+    }
     case EA_OPT_QR_PRECOND:
         if (!(value >= 0) || value > 4096) return set_err(EA_EINVAL, "QR width out of range");
         h->qr_min = (int)value;
@@ -267,6 +289,76 @@ int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget, 
                   : apply_2q_impl<float>(h, site, op, fidelity_budget, +1, f_out, 0);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free two-site update.  Its workspace lives in `scratch`, one
+// array per device for the life of the process.  In host code the array's
+// name is only a stand-in: its device address on each device is taken once,
+// with that device current, by hipGetSymbolAddress and kept in
+// g_scratch_ptr; kernels and copies only ever see that address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[EA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_ptr;  // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+int scratch_address(int dev, char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0) return set_err(EA_EINVAL, "bad device %d", dev);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_err(EA_EHIP, "hipGetSymbolAddress(scratch) failed: %s",
+                           hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return EA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mps_apply_2q_noalloc(ea_mps *h, int site, const double *op, double fidelity_budget,
+                         double *f_out) {
+    TRY(check(h));
+    if (site < 0 || site + 1 >= h->n) return set_err(EA_ERANGE, "site %d out of range", site);
+    const size_t nop = (size_t)h->d * h->d * h->d * h->d;
+    if (!op || !finite_cplx(op, nop)) return set_err(EA_EINVAL, "bad operator");
+    if (!(fidelity_budget < 0 || (fidelity_budget > 0 && fidelity_budget <= 1.0)))
+        return set_err(EA_EINVAL, "fidelity budget must be in (0, 1] or negative");
+    char *base = nullptr;
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+            (void)hipGetLastError();
+            return set_err(EA_EINVAL, "the handle's device (%d) is not the current device",
+                           h->device);
+        }
+    }
+    TRY(scratch_address(h->device, &base));
+    // event timing would create events on demand: suspended for the call
+    const bool prof = h->prof_on;
+    h->prof_on = false;
+    h->arena = base;
+    h->arena_cap = EA_NOALLOC_SCRATCH_BYTES;
+    h->arena_off = 0;
+    h->arena_saved.clear();
+    const int rc = h->f64 ? apply_2q_impl<double>(h, site, op, fidelity_budget, +1, f_out, 0)
+                          : apply_2q_impl<float>(h, site, op, fidelity_budget, +1, f_out, 0);
+    arena_release(h, 0, 0);  // every workspace buffer back to its own memory
+    h->arena = nullptr;
+    h->arena_cap = 0;
+    h->prof_on = prof;
+    return rc;
+}
 
 }  // extern "C"
 

@@ -74,6 +74,13 @@ struct ea_mps {
     int move_kind = 2;
     ea::DevBuf cq_x, cq_q, cq_g, cq_r1, cq_r2, cq_ri, cq_t, cq_misc;  // Cholesky QR workspace
     long n_chol_fallback = 0;  // Cholesky QR moves that fell back to the SVD move
+    // allocation-free calls: while `arena` is set, workspace buffers are carved
+    // from it instead of allocated (see ensure); `arena_saved` keeps every
+    // buffer's previous value, restored when the call ends
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_off = 0;
+    std::vector<std::pair<ea::DevBuf *, ea::DevBuf>> arena_saved;
+    int device = 0;  // device current when the handle was created
     bool jskip = true;  // skip block pairs unchanged since they were last examined
     ea::DevBuf ro_x64, ro_g, ro_y, ro_r, ro_t;  // re-orthogonalisation workspace
     bool reorth = true;
@@ -193,8 +200,14 @@ inline void prof_harvest(ea_mps *h) {
     h->prof_pending.clear();
 }
 
+// Tag of buffers carved from an allocation-free call's array: never freed.
+inline ea_allocator *arena_tag() {
+    static ea_allocator tag{};
+    return &tag;
+}
+
 inline void free_buf(DevBuf &b) {
-    if (b.p) {
+    if (b.p && b.al != arena_tag()) {
         if (b.al) b.al->free(b.al->ctx, b.p, b.stream);
         else (void)hipFree(b.p);
     }
@@ -203,9 +216,38 @@ inline void free_buf(DevBuf &b) {
     b.al = nullptr;
 }
 
+inline bool is_site_buf(const ea_mps *h, const DevBuf &b) {
+    return !h->site.empty() && &b >= &h->site.front() && &b <= &h->site.back();
+}
+
 // Grow b to at least `bytes` (x1.25 steps, contents not kept), from the
-// handle's allocator if it has one, else hipMalloc.
+// handle's allocator if it has one, else hipMalloc.  During an
+// allocation-free call nothing is allocated: a site tensor's buffer must
+// already hold `bytes` (else EA_ETOOBIG), and any other (workspace) buffer is
+// carved from the call's array in bump order, 256-byte aligned (EA_ETOOBIG
+// when the array is exhausted), its previous value kept for the end of the call.
 inline int ensure(ea_mps *h, DevBuf &b, size_t bytes) {
+    if (h->arena) {
+        if (is_site_buf(h, b)) {
+            if (bytes <= b.bytes) return EA_OK;
+            return set_err(EA_ETOOBIG,
+                           "allocation-free call: a site tensor needs %zu bytes, its buffer holds "
+                           "%zu (reserve bond capacity first)", bytes, b.bytes);
+        }
+        if (b.al == arena_tag() && bytes <= b.bytes) return EA_OK;
+        const size_t want = (bytes + 255) & ~size_t(255);
+        if (want > h->arena_cap - h->arena_off)
+            return set_err(EA_ETOOBIG,
+                           "allocation-free call: workspace beyond its %zu-byte device array",
+                           h->arena_cap);
+        h->arena_saved.push_back({&b, b});
+        b.p = h->arena + h->arena_off;
+        b.bytes = want;
+        b.al = arena_tag();
+        b.stream = nullptr;
+        h->arena_off += want;
+        return EA_OK;
+    }
     if (bytes <= b.bytes) return EA_OK;
     const size_t old = b.bytes;
     if (b.p) {
@@ -228,11 +270,30 @@ inline int ensure(ea_mps *h, DevBuf &b, size_t bytes) {
     return EA_OK;
 }
 
-// A result computed into `spare` becomes the content of the site buffer dst
-// (the two buffers are exchanged; `bytes` is the result's size).
+// Undo the carves made since (off, nsaved): the buffers get back their
+// previous values and the array space is free again for later work of the
+// same call (stream order keeps the earlier kernels' use of it first).
+inline void arena_release(ea_mps *h, size_t off, size_t nsaved) {
+    while (h->arena_saved.size() > nsaved) {
+        *h->arena_saved.back().first = h->arena_saved.back().second;
+        h->arena_saved.pop_back();
+    }
+    h->arena_off = off;
+}
+
+// A result computed into `spare` becomes the content of the site buffer
+// dst: normally by exchanging the two buffers; during an allocation-free call
+// (spare is then carved from the call's array) by a device copy into dst,
+// which must hold `bytes`.
 inline int commit_spare(ea_mps *h, DevBuf &dst, size_t bytes) {
-    (void)bytes;
-    std::swap(dst, h->spare);
+    if (!h->arena) {
+        std::swap(dst, h->spare);
+        return EA_OK;
+    }
+    if (bytes > dst.bytes)
+        return set_err(EA_ETOOBIG, "allocation-free call: site buffer too small (%zu < %zu)",
+                       dst.bytes, bytes);
+    HIPCHK(h, hipMemcpyAsync(dst.p, h->spare.p, bytes, hipMemcpyDeviceToDevice, h->stream));
     return EA_OK;
 }
 
@@ -603,8 +664,8 @@ void gather(ea_mps *h, const void *src, int ld, int k, int X, int conj_src, int 
 // weights); while 3r/4 exceeds it, a further step runs (three at most).
 // Well-conditioned factors need neither; wide ill-conditioned ones (thousands
 // of kept columns over several decades of singular values) take both once.
-// Workspace of reorth (taken before the caller's first write, so that a
-// failure leaves the state whole).
+// Workspace of reorth (taken before the caller's first write, so that an
+// allocation-free call fails, if it must, while the state is still whole).
 template <typename T>
 int reorth_reserve(ea_mps *h, int rows, int k, int nother) {
     if (sizeof(T) == 8 || !h->reorth || k < 1) return EA_OK;
@@ -990,15 +1051,28 @@ int move_left_cholqr(ea_mps *h) {
     return EA_OK;
 }
 
+// Space of an allocation-free call's array used by one centre move is free
+// again after it (stream order puts the move's kernels first).
+struct ArenaMark {
+    ea_mps *h;
+    size_t off, nsaved;
+    explicit ArenaMark(ea_mps *h_) : h(h_), off(h_->arena_off), nsaved(h_->arena_saved.size()) {}
+    ~ArenaMark() {
+        if (h->arena) arena_release(h, off, nsaved);
+    }
+};
+
 template <typename T>
 int move_center(ea_mps *h, int j) {
     while (h->center < j) {
+        ArenaMark am(h);
         ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
         if (h->move_kind == 2) TRY(move_right_cholqr<T>(h));
         else if (h->move_kind == 1) TRY(move_right_qr<T>(h));
         else TRY(move_right<T>(h));
     }
     while (h->center > j) {
+        ArenaMark am(h);
         ProfScope ps(h, EA_K_MOVE, 0.0, 0.0);
         if (h->move_kind == 2) TRY(move_left_cholqr<T>(h));
         else if (h->move_kind == 1) TRY(move_left_qr<T>(h));
