@@ -249,30 +249,39 @@ def bench_batched(args, torch, C, P):
 
     graph = P.capture_batched(states, progs)
 
+    t_start = [0.0]
+
+    def progress(t):
+        log(f"  layer {t} done at {time.perf_counter() - t_start[0]:.1f}s")
+
     def run_batched():
         # leading small-bond layers of all circuits: a replay of the captured
         # device-resident launch; then one batched call per remaining layer
         for st in states:
             st.reset()
-        P.run_batched(states, progs, 0.99, captured=graph)
+        t_start[0] = time.perf_counter()
+        P.run_batched(states, progs, 0.99, captured=graph, progress=progress)
 
     def run_sequential():
         for st, p in zip(states, progs):
             st.reset()
             st.run(p, 0.99)
 
-    run_batched()  # loads code objects, sizes buffers
+    if not args.single_pass:
+        run_batched()  # loads code objects, sizes buffers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_batched()
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     log(f"batched {tb:.2f}s")
-    t0 = time.perf_counter()
-    run_sequential()
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    log(f"sequential {ts:.2f}s")
+    ts = None
+    if not args.no_sequential:
+        t0 = time.perf_counter()
+        run_sequential()
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        log(f"sequential {ts:.2f}s")
     Fs = [s.fidelity_estimate()[0] for s in states]
     out = {
         "metric": "2-site gate updates/s, independent circuits advanced together, 1 GPU",
@@ -282,8 +291,12 @@ def bench_batched(args, torch, C, P):
         "data": "synthetic",
         "config": {"workload": f"batched-{len(progs)}-circuits-N20to80-depth<= {args.max_depth}",
                    "circuits": len(progs), "updates": n_upd, "f_min": 0.99, "chi_max": 1024},
-        "sequential_updates_per_s": n_upd / ts, "speedup_batched_vs_sequential": ts / tb,
+        "sequential_updates_per_s": None if ts is None else n_upd / ts,
+        "speedup_batched_vs_sequential": None if ts is None else ts / tb,
         "circuits_with_P_ge_0.99": int(sum(F >= 0.99 for F in Fs)),
+        "final_fidelity_estimates": [round(F, 6) for F in Fs],
+        "capped_updates": int(sum(sum(r["capped"] for r in s.gate_log()) for s in states)),
+        "first_pass_includes_code_loading": bool(args.single_pass),
     }
     graph.close()
     for s in states:
@@ -447,20 +460,20 @@ def bench_fig2a(args, torch, C, P):
 
 def bench_fig4(args, torch, C, P):
     """Entanglement-aware against fixed-bond-dimension simulation (Sec. VI,
-    Fig. 4 analogue, scaled down): the EA run with F_min, then the standard
-    run (every target 1, only the cap truncates) with chi_max = the largest
-    bond of the EA run.  Noiseless: 32 qubits, depth 32, F_min 0.99, complex
-    FP32.  Noisy MPO: 16 qubits, depth 16, two-qubit depolarising p = 1e-3,
-    F_min 0.95, complex FP32.  Wall time, final estimate, peak bond, and the
-    sum over updates of chi_l chi_r (bond-size work)."""
+    Fig. 4 analogue, scaled down): the EA run with F_min (bond cap 1024), then
+    the standard run (every target 1, only the cap truncates) with chi_max =
+    the largest bond of the EA run.  Noiseless: 32 qubits, depth 16, F_min
+    0.99.  Noisy MPO: 16 qubits, depth 12, two-qubit depolarising p = 1e-3,
+    F_min 0.95.  Complex FP32 (--prec).  Wall time, final estimate, peak
+    bond, capped updates and the sum over updates of chi_l chi_r."""
     rows = []
-    for kind, n, depth, f_min, noise in (("pure", 32, 32, 0.99, 0.0),
-                                         ("mixed", 16, 16, 0.95, 1e-3)):
+    for kind, n, depth, f_min, noise in (("pure", 32, 16, 0.99, 0.0),
+                                         ("mixed", 16, 12, 0.95, 1e-3)):
         prog = C.brickwork_program(n, depth, 75, kind=kind, noise_p=noise)
         res = {}
         chi_ea = None
         for mode in ("ea", "fixed"):
-            chi_max = 0 if mode == "ea" else chi_ea
+            chi_max = 1024 if mode == "ea" else chi_ea
             with P.EAState(n, kind, args.prec, chi_max=chi_max) as st:
                 run_circuit(st, C.brickwork_program(n, 2, 1, kind=kind, noise_p=noise), 1.0)
                 st.reset()
@@ -483,6 +496,44 @@ def bench_fig4(args, torch, C, P):
                      "speedup_ea_vs_fixed": res["fixed"]["seconds"] / res["ea"]["seconds"]})
     print(json.dumps({"study": "fig4-ea-vs-fixed-chi", "prec": args.prec, "rows": rows}),
           flush=True)
+
+
+def bench_vidal50(args, torch, C, P):
+    """The 50-qubit depth-20 circuit (F_min 0.99, chi <= 1024) in the
+    layer-parallel gauge (Vidal form, Hastings update; a layer's gates side by
+    side on their own streams), against the single-centre run of the same
+    build: wall time and final estimate of each."""
+    prog, cfg = C.config_program(2, depth=args.depth)
+    out_modes = {}
+    for mode in ("layer_parallel", "single_centre"):
+        st = P.EAState(prog.n_sites, "pure", args.prec, chi_max=cfg["chi_max"])
+        if mode == "layer_parallel":
+            st.set_option(P.EA_OPT_GAUGE, 1)
+        run_circuit(st, C.brickwork_program(prog.n_sites, 2, 99), 1.0)
+        st.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_circuit(st, prog, cfg["f_min"], progress=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        F, _ = st.fidelity_estimate()
+        glog = st.gate_log()
+        out_modes[mode] = {"seconds": dt, "updates_per_s": prog.n_2q / dt, "estimate": F,
+                           "capped_updates": int(sum(r["capped"] for r in glog)),
+                           "max_bond": int(max(st.bond_dims()))}
+        log(f"{mode}: {dt:.2f}s P={F:.5f}")
+        st.close()
+    lp = out_modes["layer_parallel"]
+    print(json.dumps({
+        "metric": "2-site gate updates/s, layer-parallel gauge, 1 GPU", "value": lp["updates_per_s"],
+        "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1000 * lp["seconds"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.prec == "c128" else "f32", "data": "synthetic",
+        "config": {"workload": f"brickwork-haar-50q-depth{args.depth}-Fmin0.99-chi1024-layer-parallel",
+                   "prec": args.prec},
+        "modes": out_modes,
+        "speedup_vs_single_centre": out_modes["single_centre"]["seconds"] / lp["seconds"]}),
+        flush=True)
 
 
 def bench_contraction(args, torch, C, P):
@@ -542,7 +593,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--workload", default="brickwork50",
                     choices=["brickwork50", "batched", "mpo40", "hea32", "contraction",
-                             "fig1", "fig2a", "fig4"],
+                             "fig1", "fig2a", "fig4", "vidal50"],
                     help="brickwork50: the 50-qubit depth-20 circuit (default); batched: "
                          "independent circuits of the batched workload advanced together; "
                          "mpo40: the noisy 40-qubit MPO circuit; hea32: adjoint gradients; "
@@ -551,6 +602,10 @@ def main():
                          "EA-against-fixed-bond studies at reduced sizes")
     ap.add_argument("--circuits", type=int, default=16, help="batched: number of circuits")
     ap.add_argument("--max-depth", type=int, default=12, help="batched: depth cap per circuit")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched: skip the one-circuit-after-another comparison")
+    ap.add_argument("--single-pass", action="store_true",
+                    help="batched: time the first pass (no untimed warm-up pass)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a device copy of known size (counter calibration)")
     ap.add_argument("--summarize-pmc", metavar="DIR",
@@ -580,6 +635,8 @@ def main():
         return bench_hea32(args, torch, C, P)
     if args.workload == "contraction":
         return bench_contraction(args, torch, C, P)
+    if args.workload == "vidal50":
+        return bench_vidal50(args, torch, C, P)
     if args.workload in ("fig1", "fig2a", "fig4"):
         return {"fig1": bench_fig1, "fig2a": bench_fig2a, "fig4": bench_fig4}[args.workload](
             args, torch, C, P)

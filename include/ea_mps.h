@@ -129,15 +129,34 @@ enum ea_option {
                                 rotation, so results are bit-identical); 0 examines every
                                 pair in every sweep */
     EA_OPT_QR_MOVES = 13,    /* centre moves of the update path (Sec. III): 2 (default):
-                                Cholesky QR2 in FP64 (A_c = Q R, Q the new site, R absorbed
+                                Cholesky QR in FP64 (A_c = Q R, Q the new site, R absorbed
                                 into the neighbour; matrix-core GEMMs and a blocked
-                                Cholesky), no rank dropped; a site whose condition number
+                                Cholesky; a second pass when the first Q is not orthonormal
+                                to 1e-8 for FP32 sites or 1e-13 for FP64), no rank dropped; a site whose condition number
                                 exceeds about 1e7 (a Cholesky pivot below 1e-14 of the
                                 largest diagonal entry), or whose matrix is wider than
                                 tall, moves by the Jacobi SVD instead.  1: Householder QR,
                                 no rank dropped.  0: the Jacobi SVD, dropping numerically
                                 zero singular values.  The gradient path (mps_energy_grad)
                                 always moves by SVD. */
+    EA_OPT_GAUGE_PARALLEL = 16, /* layer-parallel gauge: 1 (default) runs the gates of a layer
+                                side by side, each on a stream and host thread of its own
+                                (the same bits as one after another); 0: one after another
+                                on the state's stream. */
+    EA_OPT_GAUGE = 15,       /* 1: from a product state, switch to the layer-parallel gauge
+                                (Vidal's form, B_i = Gamma_i Lambda_{i+1} and each bond's
+                                Schmidt values; Hastings' update, no division by Lambda):
+                                the two-site updates of a layer are independent of each
+                                other (no centre moves), every gate of a layer takes its
+                                target from the estimate before the layer, and f is the
+                                kept weight of diag(Lambda_i) G (B_i B_{i+1}), exact while
+                                no truncation has happened and approximate after.  Not
+                                in the paper, which keeps one orthogonality centre
+                                (Sec. III, VI).  mps_expect, gradients, the batched small-
+                                bond launches and the allocation-free update refuse a
+                                state in this gauge (EA_EINVAL).  0: back to one centre
+                                (exact moves from the last site to the first: the centre
+                                ends on site 0). */
     EA_OPT_RESERVE_BOND = 14,/* chi > 0: grow every site tensor's buffer now to hold a
                                 (chi, d, chi) tensor (never shrunk), so that later updates up
                                 to bond chi need no new site memory, as the allocation-free

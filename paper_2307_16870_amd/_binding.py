@@ -25,7 +25,7 @@ EA_NAIVE, EA_GLOBAL, EA_NEAREST, EA_FIXED = 0, 1, 2, 3
 EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX = 0, 1, 2, 3, 4
 EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL, EA_OPT_ROT_THREADS, EA_OPT_REORTH = 5, 6, 7, 8
 EA_OPT_JACOBI_ORDER, EA_OPT_SMALL_LAYERS, EA_OPT_JACOBI_SKIP, EA_OPT_QR_PRECOND = 9, 10, 11, 12
-EA_OPT_QR_MOVES, EA_OPT_RESERVE_BOND = 13, 14
+EA_OPT_QR_MOVES, EA_OPT_RESERVE_BOND, EA_OPT_GAUGE, EA_OPT_GAUGE_PARALLEL = 13, 14, 15, 16
 EA_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 SYMBOLS = [

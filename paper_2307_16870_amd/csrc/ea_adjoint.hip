@@ -683,6 +683,7 @@ extern "C" int mps_energy_grad(ea_mps *h, int n_ops, const ea_dop *ops, const do
                                double *lnP_out) {
     TRY(check(h));
     if (h->kind != EA_PURE) return set_err(EA_EINVAL, "mps_energy_grad supports pure states");
+    if (h->gauge) return set_err(EA_EINVAL, "gradients need the single-centre gauge");
     if (n_ops < 1 || !ops) return set_err(EA_EINVAL, "no ops");
     if (n_params < 0 || (n_params > 0 && (!params || !grad_out)))
         return set_err(EA_EINVAL, "bad params");

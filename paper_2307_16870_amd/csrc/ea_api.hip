@@ -155,6 +155,9 @@ void mps_free(ea_mps *h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     prof_harvest(h);
+    for (ea_mps *w : h->workers) mps_free(w);
+    h->workers.clear();
+    if (h->ev) (void)hipEventDestroy(h->ev);
     if (h->adj_free) h->adj_free(h->adj);
     h->adj = nullptr;
     for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
@@ -164,8 +167,9 @@ void mps_free(ea_mps *h) {
                       &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_loff, &h->sm_gsite,
                       &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs,
                       &h->cq_x, &h->cq_q, &h->cq_g, &h->cq_r1, &h->cq_r2, &h->cq_ri, &h->cq_t,
-                      &h->cq_misc};
+                      &h->cq_misc, &h->cbuf, &h->ybuf};
     for (DevBuf *b : bufs) free_buf(*b);
+    for (auto &b : h->lam) free_buf(b);
     if (h->stage_host) (void)hipHostFree(h->stage_host);
     if (h->rec_host) (void)hipHostFree(h->rec_host);
     if (h->int_host) (void)hipHostFree(h->int_host);
@@ -240,6 +244,27 @@ int mps_set_option(ea_mps *h, int option, double value) {
         }
         return EA_OK;
     }
+    case EA_OPT_GAUGE_PARALLEL:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "must be 0 or 1");
+        h->vidal_parallel = value != 0;
+        return EA_OK;
+    case EA_OPT_GAUGE:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "gauge must be 0 or 1");
+        if (value == 1 && !h->gauge) {
+            for (int b = 1; b < h->n; ++b)
+                if (h->bond[b] != 1)
+                    return set_err(EA_EINVAL, "the layer-parallel gauge starts from a product state");
+            TRY(vidal_reset_lambdas(h));
+            h->gauge = 1;
+        } else if (value == 0 && h->gauge) {
+            // B_0 .. B_{N-1} contract to the state; exact moves from the last
+            // site to the first leave sites 1 .. N-1 right-normalised and the
+            // orthogonality centre on site 0
+            h->gauge = 0;
+            h->center = h->n - 1;
+            TRY(h->f64 ? move_center<double>(h, 0) : move_center<float>(h, 0));
+        }
+        return EA_OK;
     case EA_OPT_QR_PRECOND:
         if (!(value >= 0) || value > 4096) return set_err(EA_EINVAL, "QR width out of range");
         h->qr_min = (int)value;
@@ -275,6 +300,20 @@ int mps_apply_1q(ea_mps *h, int site, const double *op) {
     TRY(check(h));
     if (site < 0 || site >= h->n) return set_err(EA_ERANGE, "site %d out of range", site);
     if (!op || !finite_cplx(op, (size_t)h->d * h->d)) return set_err(EA_EINVAL, "bad operator");
+    if (h->gauge) {  // layer-parallel gauge: B_i <- g B_i, no centre to move
+        void *g = nullptr;
+        if (h->f64) {
+            TRY(stage<double>(h, op, (size_t)h->d * h->d, &g));
+            launch_apply1<double>(h->site[site].p, h->site[site].p, g, h->bond[site], h->d,
+                                  h->bond[site + 1], h->stream);
+        } else {
+            TRY(stage<float>(h, op, (size_t)h->d * h->d, &g));
+            launch_apply1<float>(h->site[site].p, h->site[site].p, g, h->bond[site], h->d,
+                                 h->bond[site + 1], h->stream);
+        }
+        LAUNCHCHK(h);
+        return EA_OK;
+    }
     return h->f64 ? apply_1q_impl<double>(h, site, op) : apply_1q_impl<float>(h, site, op);
 }
 
@@ -285,6 +324,11 @@ int mps_apply_2q(ea_mps *h, int site, const double *op, double fidelity_budget, 
     if (!op || !finite_cplx(op, nop)) return set_err(EA_EINVAL, "bad operator");
     if (!(fidelity_budget < 0 || (fidelity_budget > 0 && fidelity_budget <= 1.0)))
         return set_err(EA_EINVAL, "fidelity budget must be in (0, 1] or negative");
+    if (h->gauge) {
+        const double ft = fidelity_budget >= 0 ? fidelity_budget : schedule_target(h);
+        return h->f64 ? vidal_2q_impl<double>(h, site, op, ft, f_out, 0)
+                      : vidal_2q_impl<float>(h, site, op, ft, f_out, 0);
+    }
     return h->f64 ? apply_2q_impl<double>(h, site, op, fidelity_budget, +1, f_out, 0)
                   : apply_2q_impl<float>(h, site, op, fidelity_budget, +1, f_out, 0);
 }
@@ -329,6 +373,7 @@ extern "C" {
 int mps_apply_2q_noalloc(ea_mps *h, int site, const double *op, double fidelity_budget,
                          double *f_out) {
     TRY(check(h));
+    if (h->gauge) return set_err(EA_EINVAL, "the allocation-free update needs the single-centre gauge");
     if (site < 0 || site + 1 >= h->n) return set_err(EA_ERANGE, "site %d out of range", site);
     const size_t nop = (size_t)h->d * h->d * h->d * h->d;
     if (!op || !finite_cplx(op, nop)) return set_err(EA_EINVAL, "bad operator");
@@ -389,11 +434,150 @@ int validate_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
     return EA_OK;
 }
 
+// Layer-parallel gauge: a worker is a handle used only for its stream, pinned
+// staging and workspace, configured like the state so that a gate gives the
+// same bits on a worker as on the state's own stream.
+void copy_config(ea_mps *w, const ea_mps *h) {
+    w->n = h->n;
+    w->d = h->d;
+    w->kind = h->kind;
+    w->prec = h->prec;
+    w->chi_max = h->chi_max;
+    w->f64 = h->f64;
+    w->csz = h->csz;
+    w->tol = h->tol;
+    w->max_sweeps = h->max_sweeps;
+    w->tau = h->tau;
+    w->block = h->block;
+    w->inner_max = h->inner_max;
+    w->inner_round = h->inner_round;
+    w->jkernel = h->jkernel;
+    w->rot_threads = h->rot_threads;
+    w->jorder = h->jorder;
+    w->jskip = h->jskip;
+    w->qr_min = h->qr_min;
+    w->reorth = h->reorth;
+    w->prof_on = h->prof_on;
+    w->prof_every = h->prof_every;
+}
+
+ea_mps *make_worker(ea_mps *h, int *rc_out) {
+    ea_mps *w = new ea_mps();
+    w->alloc = h->alloc;
+    w->device = h->device;
+    copy_config(w, h);
+    *rc_out = EA_OK;
+    auto fail = [&](int rc) {
+        *rc_out = rc;
+        mps_free(w);
+        return nullptr;
+    };
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete w;
+        *rc_out = set_err(EA_EHIP, "worker stream creation failed");
+        return nullptr;
+    }
+    w->own_stream = true;
+    if (hipEventCreateWithFlags(&w->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_err(EA_EHIP, "worker event creation failed"));
+    }
+    int rc;
+    if ((rc = ensure(w, w->rec, sizeof(ea_dev_rec))) < 0) return fail(rc);
+    if ((rc = ensure(w, w->ints, 64 * sizeof(int))) < 0) return fail(rc);
+    w->stage_cap = 1u << 20;
+    if ((rc = ensure(w, w->stage_dev, w->stage_cap)) < 0) return fail(rc);
+    if (hipHostMalloc((void **)&w->stage_host, w->stage_cap, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&w->rec_host, sizeof(ea_dev_rec), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&w->int_host, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&w->dbl_host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_err(EA_ENOMEM, "pinned host allocation failed"));
+    }
+    return w;
+}
+
+// The gates of one layer in the layer-parallel gauge, each on its own worker
+// (stream and host thread), ordered after the state's pending work; the
+// state's stream then waits for all of them, and the bookkeeping is applied
+// in gate order.
+template <typename T>
+int vidal_layer_parallel(ea_mps *h, const std::vector<int> &order, const int *sites,
+                         const double *ops, size_t nop, const double *fts, const int *ranks,
+                         double *f_out) {
+    const int ng = (int)order.size();
+    while ((int)h->workers.size() < ng) {
+        int rc = EA_OK;
+        ea_mps *w = make_worker(h, &rc);
+        if (!w) return rc;
+        h->workers.push_back(w);
+    }
+    if (!h->ev) HIPCHK(h, hipEventCreateWithFlags(&h->ev, hipEventDisableTiming));
+    HIPCHK(h, hipEventRecord(h->ev, h->stream));
+    for (int u = 0; u < ng; ++u) {
+        copy_config(h->workers[u], h);
+        HIPCHK(h, hipStreamWaitEvent(h->workers[u]->stream, h->ev, 0));
+    }
+    std::vector<VidalOut> outs(ng);
+    std::vector<int> rcs(ng, EA_OK);
+    std::vector<std::string> errs(ng);
+    auto work = [&](int u) {
+        const int j = order[u];
+        ea_mps *w = h->workers[u];
+        rcs[u] = vidal_gate<T>(h, w, sites[j], ops + 2 * nop * j, fts[j], ranks ? ranks[j] : 0,
+                               &outs[u]);
+        if (rcs[u] < 0) errs[u] = g_err;
+        if (hipEventRecord(w->ev, w->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            if (rcs[u] >= 0) {
+                rcs[u] = EA_EHIP;
+                errs[u] = "event record failed";
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(ng);
+    for (int u = 1; u < ng; ++u) pool.emplace_back(work, u);
+    work(0);
+    for (auto &t : pool) t.join();
+    for (int u = 0; u < ng; ++u) HIPCHK(h, hipStreamWaitEvent(h->stream, h->workers[u]->ev, 0));
+    if (h->prof_on) {
+        for (int u = 0; u < ng; ++u) {
+            ea_mps *w = h->workers[u];
+            prof_harvest(w);
+            for (int f = 0; f < EA_K_COUNT; ++f) {
+                h->prof_ms[f] += w->prof_ms[f];
+                h->prof_flops[f] += w->prof_flops[f];
+                h->prof_bytes[f] += w->prof_bytes[f];
+                h->prof_cnt[f] += w->prof_cnt[f];
+                h->prof_timed[f] += w->prof_timed[f];
+                w->prof_ms[f] = w->prof_flops[f] = w->prof_bytes[f] = 0.0;
+                w->prof_cnt[f] = w->prof_timed[f] = 0;
+            }
+        }
+    }
+    int worst = EA_OK;
+    for (int u = 0; u < ng; ++u) {
+        const int j = order[u];
+        if (rcs[u] < 0) {
+            g_err = errs[u];
+            return rcs[u];
+        }
+        double f = 1.0;
+        const int rc = vidal_finish(h, sites[j], outs[u], &f);
+        if (rc > worst) worst = rc;
+        if (f_out) f_out[j] = f;
+    }
+    if (worst > 0) g_err = "warning during layer";
+    return worst;
+}
+
 // A layer qualifies for the device-resident path when every bond is at most
 // small_cols / d: then every factorisation of the layer has at most small_cols
 // (<= SM_N) columns.
 bool small_eligible(const ea_mps *h, int n_gates) {
-    if (h->small_cols <= 0 || n_gates < 1 || n_gates > SM_GATES) return false;
+    if (h->gauge || h->small_cols <= 0 || n_gates < 1 || n_gates > SM_GATES) return false;
     const int lim = h->small_cols / h->d;
     for (int b : h->bond)
         if (b > lim) return false;
@@ -608,6 +792,33 @@ int mps_apply_layer(ea_mps *h, int n_gates, const int *sites, const double *ops,
     const size_t nop = (size_t)h->d * h->d * h->d * h->d;
     std::vector<int> order(n_gates);
     for (int j = 0; j < n_gates; ++j) order[j] = j;
+    if (h->gauge) {
+        // layer-parallel gauge: every gate's target from the estimate before
+        // the layer; gates in increasing site order (they are independent)
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return sites[a] < sites[b]; });
+        const double ft_layer = schedule_target(h);
+        if (h->vidal_parallel && n_gates > 1) {
+            std::vector<double> fts(n_gates);
+            for (int j = 0; j < n_gates; ++j)
+                fts[j] = budgets && budgets[j] >= 0 ? budgets[j] : ft_layer;
+            return h->f64 ? vidal_layer_parallel<double>(h, order, sites, ops, nop, fts.data(),
+                                                         nullptr, f_out)
+                          : vidal_layer_parallel<float>(h, order, sites, ops, nop, fts.data(),
+                                                        nullptr, f_out);
+        }
+        int worst = EA_OK;
+        for (int j : order) {
+            double f = 1.0;
+            const double ft = budgets && budgets[j] >= 0 ? budgets[j] : ft_layer;
+            int rc = h->f64 ? vidal_2q_impl<double>(h, sites[j], ops + 2 * nop * j, ft, &f, 0)
+                            : vidal_2q_impl<float>(h, sites[j], ops + 2 * nop * j, ft, &f, 0);
+            if (rc < 0) return rc;
+            if (rc > worst) worst = rc;
+            if (f_out) f_out[j] = f;
+        }
+        if (worst > 0) g_err = "warning during layer";
+        return worst;
+    }
     const bool asc = std::abs(h->center - lo) <= std::abs(h->center - hi);
     std::sort(order.begin(), order.end(), [&](int a, int b) {
         return asc ? sites[a] < sites[b] : sites[a] > sites[b];
@@ -637,6 +848,28 @@ int mps_apply_layer_ranks(ea_mps *h, int n_gates, const int *sites, const double
     const size_t nop = (size_t)h->d * h->d * h->d * h->d;
     std::vector<int> order(n_gates);
     for (int j = 0; j < n_gates; ++j) order[j] = j;
+    if (h->gauge) {
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return sites[a] < sites[b]; });
+        const double ft_layer = schedule_target(h);
+        if (h->vidal_parallel && n_gates > 1) {
+            std::vector<double> fts(n_gates, ft_layer);
+            return h->f64 ? vidal_layer_parallel<double>(h, order, sites, ops, nop, fts.data(),
+                                                         ranks, f_out)
+                          : vidal_layer_parallel<float>(h, order, sites, ops, nop, fts.data(),
+                                                        ranks, f_out);
+        }
+        int worst = EA_OK;
+        for (int j : order) {
+            double f = 1.0;
+            int rc = h->f64 ? vidal_2q_impl<double>(h, sites[j], ops + 2 * nop * j, ft_layer, &f, ranks[j])
+                            : vidal_2q_impl<float>(h, sites[j], ops + 2 * nop * j, ft_layer, &f, ranks[j]);
+            if (rc < 0) return rc;
+            if (rc > worst) worst = rc;
+            if (f_out) f_out[j] = f;
+        }
+        if (worst > 0) g_err = "warning during layer";
+        return worst;
+    }
     const bool asc = std::abs(h->center - lo) <= std::abs(h->center - hi);
     std::sort(order.begin(), order.end(), [&](int a, int b) {
         return asc ? sites[a] < sites[b] : sites[a] > sites[b];
@@ -726,6 +959,7 @@ int mps_run_layers_batched(int n_states, ea_mps *const *hs, const int *n_layers,
         return set_err(EA_EINVAL, "null argument");
     for (int b = 0; b < n_states; ++b) {
         TRY(check(hs[b]));
+        if (hs[b]->gauge) return set_err(EA_EINVAL, "state %d is in the layer-parallel gauge", b);
         for (int c = 0; c < b; ++c)
             if (hs[c] == hs[b]) return set_err(EA_EINVAL, "a state appears twice in the batch");
         if (n_layers[b] < 0) return set_err(EA_EINVAL, "n_layers < 0");
@@ -786,6 +1020,7 @@ int mps_fidelity_estimate(const ea_mps *h, double *F_out, double *lnF_out) {
 int mps_expect(ea_mps *h, int n_terms, const int *sites, const int *widths, const double *ops,
                double *out) {
     TRY(check(h));
+    if (h->gauge) return set_err(EA_EINVAL, "mps_expect needs the single-centre gauge (EA_OPT_GAUGE 0)");
     if (n_terms < 0 || (n_terms > 0 && (!sites || !widths || !ops || !out)))
         return set_err(EA_EINVAL, "bad arguments");
     size_t nops = 0;
@@ -855,6 +1090,7 @@ int mps_load(ea_mps *h, const int *bond_dims, const double *data, int center) {
     }
     if (center < 0 || center >= h->n) return set_err(EA_ERANGE, "bad centre");
     if (!finite_cplx(data, tot)) return set_err(EA_EINVAL, "non-finite data");
+    h->gauge = 0;  // loaded tensors: one orthogonality centre
     return h->f64 ? load_impl<double>(h, bond_dims, data, center)
                   : load_impl<float>(h, bond_dims, data, center);
 }
@@ -891,6 +1127,7 @@ int mps_reset_product(ea_mps *h, const double *local) {
     h->g = 0;
     h->has_sched = false;
     h->log.clear();
+    if (h->gauge) TRY(vidal_reset_lambdas(h));  // the gauge is kept; every bond value 1
     return EA_OK;
 }
 
@@ -1026,6 +1263,7 @@ int mps_program_capture(int n_states, ea_mps *const *hs, const int *n_layers,
         return set_err(EA_EINVAL, "null argument");
     for (int b = 0; b < n_states; ++b) {
         TRY(check(hs[b]));
+        if (hs[b]->gauge) return set_err(EA_EINVAL, "state %d is in the layer-parallel gauge", b);
         for (int c = 0; c < b; ++c)
             if (hs[c] == hs[b]) return set_err(EA_EINVAL, "a state appears twice in the program");
         if (n_layers[b] < 0) return set_err(EA_EINVAL, "n_layers < 0");

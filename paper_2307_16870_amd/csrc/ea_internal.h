@@ -74,6 +74,15 @@ struct ea_mps {
     int move_kind = 2;
     ea::DevBuf cq_x, cq_q, cq_g, cq_r1, cq_r2, cq_ri, cq_t, cq_misc;  // Cholesky QR workspace
     long n_chol_fallback = 0;  // Cholesky QR moves that fell back to the SVD move
+    long n_cholqr_single = 0;  // Cholesky QR moves that needed one pass
+    // layer-parallel gauge (Vidal form, Hastings update): site tensors hold
+    // B_i = Gamma_i Lambda_{i+1}; lam[b] the FP64 Schmidt values of bond b
+    int gauge = 0;  // 0: one orthogonality centre; 1: layer-parallel
+    std::vector<ea::DevBuf> lam;
+    ea::DevBuf cbuf, ybuf;  // the unscaled two-site block; the kept right vectors
+    std::vector<ea_mps *> workers;  // per-gate stream and workspace of a layer run side by side
+    hipEvent_t ev = nullptr;        // orders a layer's streams
+    bool vidal_parallel = true;     // run a layer's gates side by side
     // allocation-free calls: while `arena` is set, workspace buffers are carved
     // from it instead of allocated (see ensure); `arena_saved` keeps every
     // buffer's previous value, restored when the call ends
@@ -908,12 +917,22 @@ int move_left_qr(ea_mps *h) {
 // the state is touched and the Jacobi SVD move runs instead.
 constexpr double CHOLQR_PIVOT_REL = 1e-14;
 
-// Two passes of Cholesky QR on the FP64 matrix X (rows x cols, row-major,
-// rows >= cols) when `cols_orth` (Q has orthonormal columns, X = Q R), else on
-// X (rows x cols, cols >= rows) with orthonormal rows (X = R^H Q).  Q is left
-// in cq_x, R = R2 R1 in cq_g (cols x cols or rows x rows).  Returns 1 if a
-// Cholesky broke down (state untouched), 0 on success, < 0 on error.
-inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_orth) {
+// Orthogonality (||Q^H Q - I||_F) at which one Cholesky QR pass suffices: far
+// below the working precision's rounding (Q is stored in it), 1e-8 for FP32
+// sites and 1e-13 for FP64 sites.
+template <typename T>
+constexpr double cholqr_skip_tol() { return sizeof(T) == 4 ? 1e-8 : 1e-13; }
+
+// Cholesky QR on the FP64 matrix X (rows x cols, row-major, rows >= cols)
+// when `cols_orth` (Q has orthonormal columns, X = Q R), else on X (rows x
+// cols, cols >= rows) with orthonormal rows (X = R^H Q).  The first pass's Q1
+// is checked through the next pass's Gram matrix G2 = Q1^H Q1 (or Q1 Q1^H):
+// when ||G2 - I||_F <= skip_tol, Q1 and R1 are kept (one pass, one Cholesky);
+// otherwise G2 is factored as well (Cholesky QR2).  Q is left in cq_x, R in
+// cq_g (cols x cols or rows x rows).  Returns 1 if a Cholesky broke down
+// (state untouched), 0 on success, < 0 on error.
+inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_orth,
+                   double skip_tol) {
     const int n = cols_orth ? cols : rows;  // order of the Gram matrix
     const size_t nx = (size_t)rows * cols, nn = (size_t)n * n;
     TRY(ensure(h, h->cq_q, 16 * nx));
@@ -923,36 +942,57 @@ inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_ort
     TRY(ensure(h, h->cq_r2, 16 * nn));
     TRY(ensure(h, h->cq_ri, 16 * nn));
     TRY(ensure(h, h->cq_t, 16 * nn));
-    TRY(ensure(h, h->cq_misc, 256));
+    TRY(ensure(h, h->cq_misc, 256 + 8 * (size_t)((n + 3) / 4)));
     double *dmax = (double *)h->cq_misc.p;
+    double *fro2 = dmax + 1;
     int *flag = (int *)((char *)h->cq_misc.p + 64);
+    double *part = (double *)((char *)h->cq_misc.p + 256);
     launch_fill_int(flag, 1, 0, h->stream);
-    const double *src = X;
-    for (int pass = 0; pass < 2; ++pass) {
-        void *Rk = pass == 0 ? h->cq_r1.p : h->cq_r2.p;
-        void *dst = pass == 0 ? h->cq_q.p : h->cq_x.p;
-        {
-            ProfScope ps(h, EA_K_QR, 8.0 * (double)nx * n + 8.0 * (double)nn * n, 16.0 * (2.0 * nx + 3.0 * nn));
-            if (cols_orth)  // G = X^H X, Q = X R^{-1}
-                launch_zgemm<double>(1, 0, n, n, rows, 1.0, 0.0, src, cols, src, cols, 0.0, 0.0,
-                                     h->cq_g.p, n, h->stream);
-            else  // G = X X^H, Q = R^{-H} X
-                launch_zgemm<double>(0, 1, n, n, cols, 1.0, 0.0, src, cols, src, cols, 0.0, 0.0,
-                                     h->cq_g.p, n, h->stream);
-            launch_cholesky_inv(h->cq_g.p, Rk, h->cq_ri.p, h->cq_t.p, n, dmax, CHOLQR_PIVOT_REL,
-                                flag, h->stream);
-            if (cols_orth)
-                launch_zgemm<double>(0, 0, rows, cols, n, 1.0, 0.0, src, cols, h->cq_ri.p, n, 0.0,
-                                     0.0, dst, cols, h->stream);
-            else
-                launch_zgemm<double>(1, 0, rows, cols, n, 1.0, 0.0, h->cq_ri.p, n, src, cols, 0.0,
-                                     0.0, dst, cols, h->stream);
-        }
-        src = (const double *)dst;
+    const double fl_gram = 8.0 * (double)nx * n, fl_chol = 8.0 * (double)nn * n;
+    auto gram = [&](const void *src) {
+        if (cols_orth)  // G = X^H X
+            launch_zgemm<double>(1, 0, n, n, rows, 1.0, 0.0, src, cols, src, cols, 0.0, 0.0,
+                                 h->cq_g.p, n, h->stream);
+        else  // G = X X^H
+            launch_zgemm<double>(0, 1, n, n, cols, 1.0, 0.0, src, cols, src, cols, 0.0, 0.0,
+                                 h->cq_g.p, n, h->stream);
+    };
+    auto factor_apply = [&](const void *src, void *Rk, void *dst) {
+        launch_cholesky_inv(h->cq_g.p, Rk, h->cq_ri.p, h->cq_t.p, n, dmax, CHOLQR_PIVOT_REL,
+                            flag, h->stream);
+        if (cols_orth)  // Q = X R^{-1}
+            launch_zgemm<double>(0, 0, rows, cols, n, 1.0, 0.0, src, cols, h->cq_ri.p, n, 0.0,
+                                 0.0, dst, cols, h->stream);
+        else  // Q = R^{-H} X
+            launch_zgemm<double>(1, 0, rows, cols, n, 1.0, 0.0, h->cq_ri.p, n, src, cols, 0.0,
+                                 0.0, dst, cols, h->stream);
+    };
+    {
+        ProfScope ps(h, EA_K_QR, 2.0 * fl_gram + fl_chol, 16.0 * (3.0 * nx + 3.0 * nn));
+        gram(X);
+        factor_apply(X, h->cq_r1.p, h->cq_q.p);
+        gram(h->cq_q.p);  // G2 of Q1
+        launch_offident_fro2(h->cq_g.p, n, part, fro2, h->stream);
     }
-    // R = R2 R1 (upper triangular products)
-    launch_zgemm<double>(0, 0, n, n, n, 1.0, 0.0, h->cq_r2.p, n, h->cq_r1.p, n, 0.0, 0.0,
-                         h->cq_g.p, n, h->stream);
+    LAUNCHCHK(h);
+    HIPCHK(h, hipMemcpyAsync(h->int_host, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->dbl_host, fro2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    prof_harvest(h);
+    if (h->int_host[0] != 0) return 1;
+    if (std::sqrt(h->dbl_host[0]) <= skip_tol) {  // Q1 orthonormal enough: one pass
+        std::swap(h->cq_q, h->cq_x);
+        std::swap(h->cq_g, h->cq_r1);
+        h->n_cholqr_single += 1;
+        return 0;
+    }
+    {
+        ProfScope ps(h, EA_K_QR, fl_gram + 2.0 * fl_chol, 16.0 * (2.0 * nx + 3.0 * nn));
+        factor_apply(h->cq_q.p, h->cq_r2.p, h->cq_x.p);
+        // R = R2 R1 (upper triangular products)
+        launch_zgemm<double>(0, 0, n, n, n, 1.0, 0.0, h->cq_r2.p, n, h->cq_r1.p, n, 0.0, 0.0,
+                             h->cq_g.p, n, h->stream);
+    }
     LAUNCHCHK(h);
     HIPCHK(h, hipMemcpyAsync(h->int_host, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -997,7 +1037,7 @@ int move_right_cholqr(ea_mps *h) {
     const size_t nx = (size_t)M * N;
     const double *X = nullptr;
     TRY(site_c128<T>(h, c, nx, &X));
-    const int rc = cholqr2(h, X, M, N, true);
+    const int rc = cholqr2(h, X, M, N, true, cholqr_skip_tol<T>());
     if (rc < 0) return rc;
     if (rc == 1) {  // ill-conditioned: the SVD move
         h->n_chol_fallback += 1;
@@ -1029,7 +1069,7 @@ int move_left_cholqr(ea_mps *h) {
     const size_t nx = (size_t)M * N;
     const double *X = nullptr;
     TRY(site_c128<T>(h, c, nx, &X));
-    const int rc = cholqr2(h, X, M, N, false);
+    const int rc = cholqr2(h, X, M, N, false, cholqr_skip_tol<T>());
     if (rc < 0) return rc;
     if (rc == 1) {
         h->n_chol_fallback += 1;
@@ -1157,6 +1197,141 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
     if (f_out) *f_out = rec.f;
     if (rec.capped) return set_err(EA_WARN_CAPPED, "chi_max bound at gate %ld", (long)r.gate);
     if (!rec.converged) return set_err(EA_WARN_NOCONV, "Jacobi did not converge");
+    return EA_OK;
+}
+
+// Two-site update in the layer-parallel gauge (Vidal form, Hastings'
+// division-free update; gates of one layer touch disjoint sites and bonds):
+//   C = G (B_i B_{i+1}),  Theta = diag(Lambda_i) C = X S Y^H,  k kept (Sec. VI),
+//   B_{i+1} <- Y_k^H,  B_i <- C Y_k / ||s_k||,  Lambda_{i+1} <- s_k / ||s_k||,
+// f = sum_kept s^2 / sum s^2 (Eqs. 10-11; exact while the form is exact).
+// The device work of one gate runs on the workspace and stream of `w` (the
+// state's own, or a worker's for gates run side by side); it writes only
+// sites i, i+1 and bond value i+1 of the state h.  The scalar bookkeeping
+// (bond, estimate, log) is vidal_finish, applied in gate order.
+struct VidalOut {
+    ea_dev_rec rec{};
+    int chi_l = 0, chi_m = 0, chi_r = 0;
+    double f_t = 1.0;
+};
+
+template <typename T>
+int vidal_gate(ea_mps *h, ea_mps *w, int i, const double *op, double f_t, int forced_k,
+               VidalOut *out) {
+    f_t = std::min(1.0, std::max(f_t, 1e-300));
+    const int d = h->d, chiL = h->bond[i], chiM = h->bond[i + 1], chiR = h->bond[i + 2];
+    const int M = d * chiL, N = d * chiR;
+    const int orient = M >= N ? 0 : 1, mw = std::max(M, N), nw = std::min(M, N);
+    if (nw > EA_SORT_MAX) return set_err(EA_ETOOBIG, "two-site matrix too large (%d)", nw);
+    TRY(ensure(w, w->W, w->csz * (size_t)mw * nw));
+    TRY(ensure(w, w->V, w->csz * (size_t)nw * nw));
+    TRY(ensure(w, w->cbuf, w->csz * (size_t)mw * nw));
+    void *G = nullptr;
+    TRY(stage<T>(w, op, (size_t)d * d * d * d, &G));
+    {
+        const double dd = d;
+        ProfScope ps(w, EA_K_THETA,
+                     8.0 * dd * dd * chiL * (double)chiM * chiR + 8.0 * dd * dd * dd * dd * chiL * (double)chiR,
+                     (double)w->csz * (dd * chiL * chiM + dd * chiM * (double)chiR +
+                                       dd * dd * chiL * (double)chiR + dd * dd * dd * dd));
+        if (sizeof(T) == 4 && w->prec == EA_C64_BF16X3)
+            launch_theta_bf16x3(h->site[i].p, h->site[i + 1].p, G, w->W.p, chiL, chiM, chiR, d,
+                                orient, w->stream);
+        else
+            launch_theta_mfma<T>(h->site[i].p, h->site[i + 1].p, G, w->W.p, chiL, chiM, chiR, d,
+                                 orient, w->stream);
+    }
+    {
+        ProfScope ps(w, EA_K_OTHER, 0.0, 3.0 * (double)w->csz * mw * (double)nw);
+        HIPCHK(w, hipMemcpyAsync(w->cbuf.p, w->W.p, w->csz * (size_t)mw * nw,
+                                 hipMemcpyDeviceToDevice, w->stream));
+        launch_scale_lambda<T>(w->W.p, mw, nw, orient, (const double *)h->lam[i].p, d, w->stream);
+    }
+    LAUNCHCHK(w);
+    TRY(factor_and_decide<T>(w, mw, nw, f_t, 0, forced_k));  // syncs w's stream
+    const ea_dev_rec rec = *w->rec_host;
+    const int k = rec.k;
+    if (!(rec.s0 > 0.0) || !std::isfinite(rec.total))
+        return set_err(EA_EINVAL, "the operator annihilates the state (all singular values 0)");
+    // the state's buffers of sites i, i+1 were last read by this gate's
+    // contraction, which has completed (w's stream was synchronised above)
+    TRY(ensure(h, h->site[i], h->csz * (size_t)M * k));
+    TRY(ensure(h, h->site[i + 1], h->csz * (size_t)k * N));
+    TRY(ensure(h, h->lam[i + 1], sizeof(double) * (size_t)k));
+    TRY(ensure(w, w->ybuf, w->csz * (size_t)N * k));
+    TRY(reorth_reserve<T>(w, N, k, M));
+    // Y_k (N x k, row-major) and B_{i+1} = Y_k^H: the right singular vectors
+    // are V's columns (orient 0) or W's columns over s (orient 1, W = Theta^H)
+    const void *ysrc = orient == 0 ? w->V.p : w->W.p;
+    const int es = orient == 0 ? 0 : -1;
+    gather<T>(w, ysrc, N, k, N, 0, es, 0, 1, w->ybuf.p);
+    gather<T>(w, ysrc, N, k, N, 1, es, 0, 0, h->site[i + 1].p);
+    {
+        // B_i = C Y_k / ||s_k||; cbuf holds C column-major (orient 0: its
+        // row-major view is C^T) or C^H column-major (orient 1: view conj(C))
+        ProfScope ps(w, EA_K_GEMM, 8.0 * M * (double)N * k,
+                     (double)w->csz * ((double)M * N + (double)N * k + (double)M * k));
+        launch_zgemm<T>(orient == 0 ? 2 : 3, 0, M, k, N, rec.scale, 0.0, w->cbuf.p,
+                        orient == 0 ? M : N, w->ybuf.p, k, 0.0, 0.0, h->site[i].p, k, w->stream);
+    }
+    launch_vidal_lambda((const double *)w->s_sorted.p, (const ea_dev_rec *)w->rec.p, k,
+                        (double *)h->lam[i + 1].p, w->stream);
+    LAUNCHCHK(w);
+    TRY(reorth<T>(w, false, h->site[i + 1].p, N, k, h->site[i].p, M));
+    out->rec = rec;
+    out->chi_l = chiL;
+    out->chi_m = chiM;
+    out->chi_r = chiR;
+    out->f_t = f_t;
+    return EA_OK;
+}
+
+// Bookkeeping of one layer-parallel update (in gate order).
+inline int vidal_finish(ea_mps *h, int i, const VidalOut &o, double *f_out) {
+    const ea_dev_rec &rec = o.rec;
+    h->bond[i + 1] = rec.k;
+    h->lnP += rec.lnf;
+    if (h->kind == EA_MIXED && rec.kept2 > 0) h->lnS += 0.5 * std::log(rec.kept2);
+    ea_gate_record r;
+    r.gate = h->g;
+    r.site = i;
+    r.chi_l = o.chi_l;
+    r.chi_m = o.chi_m;
+    r.chi_r = o.chi_r;
+    r.k = rec.k;
+    r.k_f = rec.k_f;
+    r.sweeps = rec.sweeps;
+    r.capped = rec.capped;
+    r.f_t = o.f_t;
+    r.f = rec.f;
+    r.total = rec.total;
+    r.lnP = h->lnP;
+    r.lnS = h->lnS;
+    h->log.push_back(r);
+    h->g += 1;
+    if (f_out) *f_out = rec.f;
+    if (rec.capped) return set_err(EA_WARN_CAPPED, "chi_max bound at gate %ld", (long)r.gate);
+    if (!rec.converged) return set_err(EA_WARN_NOCONV, "Jacobi did not converge");
+    return EA_OK;
+}
+
+// One gate on the state's own stream.
+template <typename T>
+int vidal_2q_impl(ea_mps *h, int i, const double *op, double f_t, double *f_out, int forced_k) {
+    VidalOut o;
+    TRY(vidal_gate<T>(h, h, i, op, f_t, forced_k, &o));
+    return vidal_finish(h, i, o, f_out);
+}
+
+// Bond values of a product state in the layer-parallel gauge: every bond 1.
+inline int vidal_reset_lambdas(ea_mps *h) {
+    h->lam.resize(h->n + 1);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const double one = 1.0;
+    for (int b = 0; b <= h->n; ++b) {
+        TRY(ensure(h, h->lam[b], sizeof(double)));
+        HIPCHK(h, hipMemcpy(h->lam[b].p, &one, sizeof(double), hipMemcpyHostToDevice));
+    }
     return EA_OK;
 }
 

@@ -48,7 +48,8 @@ void launch_theta_bf16x3(const void *A, const void *B, const void *G, void *W, i
                          int chiM, int chiR, int d, int orient, hipStream_t s);
 // C (M x N) = alpha op(A) op(B) + beta C on the matrix cores (k_zgemm.hip),
 // row-major with leading dimensions; op 0: as stored (A is M x K), 1:
-// conjugate transpose (A stored K x M), 2: transpose (A stored K x M).
+// conjugate transpose (A stored K x M), 2: transpose (A stored K x M), 3:
+// conjugate (A stored M x K).
 template <typename T>
 void launch_zgemm(int opA, int opB, int M, int N, int K, double ar, double ai, const void *A,
                   int lda, const void *B, int ldb, double br, double bi, void *C, int ldc,
@@ -61,6 +62,9 @@ void launch_zgemm(int opA, int opB, int M, int N, int K, double ar, double ai, c
 constexpr int CHOL_NB = 32;
 void launch_cholesky_inv(void *G, void *R, void *Rinv, void *T1, int n, double *dmax,
                          double rel_min, int *flag, hipStream_t s);
+// ||G - I||_F^2 of an n x n complex FP64 matrix into *out (device); part is
+// scratch of (n + 3) / 4 doubles.
+void launch_offident_fro2(const void *G, int n, double *part, double *out, hipStream_t s);
 // The same for `batch` independent products, entry b taking its operands at
 // A + b sA, B + b sB, C + b sC (complex elements).
 template <typename T>
@@ -68,6 +72,14 @@ void launch_zgemm_batched(int opA, int opB, int M, int N, int K, double ar, doub
                           const void *A, int lda, size_t sA, const void *B, int ldb, size_t sB,
                           double br, double bi, void *C, int ldc, size_t sC, int batch,
                           hipStream_t s);
+// Layer-parallel gauge (k_vidal.hip): scale row (l, s) of Theta by lam[l],
+// W holding Theta (orient 0, rows = d chi_l) or Theta^H (orient 1) column-major;
+// lam_out[j] = s_sorted[j] * rec->scale for j < k.
+template <typename T>
+void launch_scale_lambda(void *W, int rows, int cols, int orient, const double *lam, int d,
+                         hipStream_t s);
+void launch_vidal_lambda(const double *s_sorted, const ea_dev_rec *rec, int k, double *lam_out,
+                         hipStream_t s);
 // C (M x N) = A (M x K) * B (K x N), row-major with leading dimensions.
 template <typename T>
 void launch_gemm(const void *A, const void *B, void *C, int M, int N, int K, int lda, int ldb,

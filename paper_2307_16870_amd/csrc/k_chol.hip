@@ -122,7 +122,49 @@ __global__ void k_lower_zero(cx<double> *__restrict__ A, int n) {
     if (r > c) A[idx] = zero_cx<double>();
 }
 
+// Partial sums of |G - I|^2 over rows: block b takes rows 4b .. 4b+3.
+__global__ __launch_bounds__(256) void k_offident_part(const cx<double> *__restrict__ G, int n,
+                                                       double *__restrict__ part) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int r = 4 * blockIdx.x; r < min(n, 4 * (int)blockIdx.x + 4); ++r)
+        for (int c = threadIdx.x; c < n; c += 256) {
+            cx<double> v = G[(size_t)r * n + c];
+            if (r == c) v.x -= 1.0;
+            acc += v.x * v.x + v.y * v.y;
+        }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double *__restrict__ part, int np,
+                                                   double *__restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 }  // namespace
+
+// ||G - I||_F^2 of an n x n matrix into *out; part is scratch of (n + 3) / 4
+// doubles.
+void launch_offident_fro2(const void *G, int n, double *part, double *out, hipStream_t s) {
+    const int nb = (n + 3) / 4;
+    k_offident_part<<<nb, 256, 0, s>>>((const cx<double> *)G, n, part);
+    k_sum_parts<<<1, 256, 0, s>>>(part, nb, out);
+}
 
 // Cholesky G = R^H R (G overwritten by its trailing updates) and Rinv = R^{-1}.
 // T1 is scratch of n x n.  *flag is set (not cleared) on a breakdown.

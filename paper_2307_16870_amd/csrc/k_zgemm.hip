@@ -6,7 +6,8 @@
 //
 //   C (M x N) = alpha op(A) op(B) + beta C,  row-major, leading dimensions
 //   lda / ldb / ldc; op 0: the matrix as stored (A is M x K), 1: conjugate
-//   transpose (A stored K x M), 2: transpose (A stored K x M).
+//   transpose (A stored K x M), 2: transpose (A stored K x M), 3: conjugate
+//   (A stored M x K).
 //
 // 64 x 64 output tile per workgroup of four waves (2 x 2 waves of 32 x 32,
 // i.e. 2 x 2 MFMA tiles of 16 x 16 each), K in stages of 16.  Real and
@@ -86,9 +87,11 @@ __global__ __launch_bounds__(256) void k_zgemm(int opA, int opB, int M, int N, i
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = blockIdx.y * ZT, n0 = blockIdx.x * ZT;
-    // op(A)[m][k]: A[m lda + k] (op 0) or A[k lda + m] (ops 1, 2); op(B)[k][n],
-    // staged as its transpose: B[k ldb + n] (op 0) or B[n ldb + k] (ops 1, 2)
-    const bool cpA = opA != 0, cjA = opA == 1, cpB = opB == 0, cjB = opB == 1;
+    // op(A)[m][k]: A[m lda + k] (ops 0, 3) or A[k lda + m] (ops 1, 2); op(B)[k][n],
+    // staged as its transpose: B[k ldb + n] (ops 0, 3) or B[n ldb + k] (ops 1, 2);
+    // ops 1 and 3 conjugate
+    const bool cpA = opA == 1 || opA == 2, cjA = opA == 1 || opA == 3;
+    const bool cpB = opB == 0 || opB == 3, cjB = opB == 1 || opB == 3;
     typename MF::acc re[2][2], im[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)

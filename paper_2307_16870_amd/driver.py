@@ -153,14 +153,15 @@ def capture_batched(states, programs):
 
 
 def run_batched(states, programs, f_min=1.0, strategy=B.EA_GLOBAL, persistent=True,
-                captured=None):
+                captured=None, progress=None):
     """Advance independent states through their programs together.  With
     ``persistent`` the leading small-bond layers of all states run in one
     device-resident launch (``mps_run_layers_batched``, or a replay of
     ``captured`` from ``capture_batched`` on the same states and programs);
     then every remaining layer is one ``mps_apply_layer_batched`` call over
     the states that still have it.  Programs must hold two-qubit gates only.
-    Returns the worst status seen."""
+    ``progress(t)``, if given, is called after each such layer.  Returns the
+    worst status seen."""
     for st, p in zip(states, programs):
         st.set_schedule(f_min, max(1, p.n_2q), strategy)
     done = [0] * len(states)
@@ -181,4 +182,6 @@ def run_batched(states, programs, f_min=1.0, strategy=B.EA_GLOBAL, persistent=Tr
         ops = [np.stack([op.mat for op in programs[b].layers[t]]) for b in idx]
         rc, _, _ = B.mps_apply_layer_batched([states[b].h for b in idx], sites, ops)
         worst = max(worst, rc)
+        if progress is not None:
+            progress(t)
     return worst
