@@ -718,6 +718,11 @@ def main():
                        "updates keep less weight than their target, so the estimate ends "
                        "below F_min" if F < f_min else "estimate at or above F_min"),
         "max_bond": int(max(st.bond_dims())),
+        "jacobi_sweeps": {
+            "mean": sum(r["sweeps"] for r in glog_full) / max(1, len(glog_full)),
+            "mean_at_width_ge_1024": (lambda L: sum(L) / max(1, len(L)))(
+                [r["sweeps"] for r in glog_full if 2 * min(r["chi_l"], r["chi_r"]) >= 1024]),
+            "max": max((r["sweeps"] for r in glog_full), default=0)},
         "kernels_ms": {k: round(v["ms"], 3) for k, v in fams.items()},
         "roofline": roofline,
         "rooflines_other": {k: roof(k) for k in ["jacobi_apply", "jacobi_gram", "theta"]

@@ -329,8 +329,24 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         const int lane = tid % 64;
         src_j = (lane & ~(NP - 1)) | (sl_j < w ? (sl_j + 1) % w : sl_j);
     }
+    // With skipping on, a pair none of whose column pairs is out of tolerance
+    // runs no inner sweep: no rotation would change G, so every later step
+    // would see exactly the values checked here and again rotate nothing.
+    bool need = true;
+    if (stamp) {
+        bool any = false;
+        for (int e = tid; e < NC * NC && !any; e += NTH) {
+            const int p = e / NC, q = e % NC;
+            const bool cand = inter ? (p < na && q >= na && q < nc) : (p < q && q < nc);
+            if (cand) {
+                JRot<T> rt;
+                any = jacobi_rotation(G[p][p].x, G[q][q].x, G[p][q], tol, rt);
+            }
+        }
+        need = __syncthreads_or(any) != 0;
+    }
     int first = 0;
-    if (nc >= 2 && (!inter || (na > 0 && nc > na))) {
+    if (need && nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
             const int slot = isw & 1;
             if (tid < npairs) rec_[0][tid] = make_rot(tid, 0, slot);
@@ -427,10 +443,13 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         }
         __syncthreads();
     }
+    // J is read only for a pair that rotated (the apply kernel checks rotflag)
     cx<T> *jo = Jout + (size_t)pair * NC * NC;
-    for (int e = tid; e < NC * NC; e += NTH) {
-        const int p = e / NC, q = e % NC;
-        jo[e] = (p < nc && q < nc) ? J[p][q] : zero_cx<T>();
+    if (first > 0) {
+        for (int e = tid; e < NC * NC; e += NTH) {
+            const int p = e / NC, q = e % NC;
+            jo[e] = (p < nc && q < nc) ? J[p][q] : zero_cx<T>();
+        }
     }
     if (tid == 0) {
         rotflag[pair] = first > 0 ? 1 : 0;
