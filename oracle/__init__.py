@@ -17,6 +17,11 @@ Everything here is plain, slow and complex128:
   simulators and the fidelities of Eqs. (7) and (9).
 * :mod:`oracle.adjoint` -- FP64 reverse-mode gradient of an energy through
   the updates with kept ranks frozen.
+* :mod:`oracle.vidal`   -- the layer-parallel gauge (Vidal form, Hastings'
+  update): all disjoint gates of a layer from the estimate before it.
+* :mod:`oracle.topk`    -- the partial (top-k) factorisation: randomized
+  subspace iteration from a SplitMix64 start block, the kept rank from the
+  Ritz values plus the weight outside the subspace.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test against
 brute force, a closed form, an invariant or a library routine, except the
