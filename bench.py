@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -332,6 +333,18 @@ def bench_mpo40(args, torch, C, P):
         "capped_updates": int(sum(r["capped"] for r in glog)),
         "max_bond": int(max(st.bond_dims())),
     }
+    # the running estimate after each layer, and where the bond cap first bites
+    per_layer, pos, first_cap = [], 0, None
+    for li, layer in enumerate(prog.layers):
+        recs = glog[pos:pos + len(layer)]
+        pos += len(layer)
+        if recs:
+            per_layer.append(round(math.exp(recs[-1]["lnP"]), 6))
+            if first_cap is None and any(r["capped"] for r in recs):
+                first_cap = li + 1
+    out["estimate_after_layer"] = per_layer
+    out["first_layer_with_capped_update"] = first_cap
+    out["layers_with_estimate_ge_f_min"] = sum(1 for v in per_layer if v >= cfg["f_min"])
     st.close()
     print(json.dumps(out), flush=True)
 
