@@ -312,6 +312,8 @@ def bench_mpo40(args, torch, C, P):
     prog, cfg = C.config_program(3, depth=args.depth if args.depth != 20 else 30)
     stream = torch.cuda.current_stream()
     st = P.EAState(prog.n_sites, "mixed", args.prec, chi_max=cfg["chi_max"], stream=stream)
+    if args.topk:
+        st.set_option(P.EA_OPT_TOPK, 1)
     tiny = C.config_program(3, depth=2)[0]
     run_circuit(st, tiny, 1.0)
     torch.cuda.synchronize()
@@ -332,7 +334,10 @@ def bench_mpo40(args, torch, C, P):
         "final_fidelity_estimate": F,
         "capped_updates": int(sum(r["capped"] for r in glog)),
         "max_bond": int(max(st.bond_dims())),
+        "partial_factorisations": int(sum(r["subspace"] > 0 for r in glog)),
     }
+    if args.topk:
+        out["config"]["topk"] = True
     # the running estimate after each layer, and where the bond cap first bites
     per_layer, pos, first_cap = [], 0, None
     for li, layer in enumerate(prog.layers):
@@ -602,6 +607,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the untimed-by-contract FP64 comparison circuit")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--topk", action="store_true",
+                    help="partial (top-k) factorisation of eligible updates (EA_OPT_TOPK)")
     ap.add_argument("--cpu-layers", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--workload", default="brickwork50",
@@ -658,6 +665,8 @@ def main():
     f_min, chi_max = cfg["f_min"], cfg["chi_max"]
 
     st = P.EAState(prog.n_sites, "pure", args.prec, chi_max=chi_max, stream=stream)
+    if args.topk:
+        st.set_option(P.EA_OPT_TOPK, 1)
     # load the kernels' code objects before anything is timed (not a step)
     tiny = C.brickwork_program(prog.n_sites, 2, 99)
     run_circuit(st, tiny, 1.0)
@@ -722,7 +731,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"brickwork-haar-50q-depth{args.depth}-Fmin0.99-chi1024",
                    "n_qubits": prog.n_sites, "depth": args.depth, "updates_per_step": prog.n_2q,
-                   "f_min": f_min, "chi_max": chi_max, "schedule": "global", "prec": args.prec},
+                   "f_min": f_min, "chi_max": chi_max, "schedule": "global", "prec": args.prec,
+                   **({"topk": True} if args.topk else {})},
         "circuit_time_s": ms_step / 1000.0,
         "final_fidelity_estimate": F,
         "capped_updates": int(sum(r["capped"] for r in glog_full)),
@@ -731,6 +741,7 @@ def main():
                        "updates keep less weight than their target, so the estimate ends "
                        "below F_min" if F < f_min else "estimate at or above F_min"),
         "max_bond": int(max(st.bond_dims())),
+        "partial_factorisations": int(sum(r["subspace"] > 0 for r in glog_full)),
         "jacobi_sweeps": {
             "mean": sum(r["sweeps"] for r in glog_full) / max(1, len(glog_full)),
             "mean_at_width_ge_1024": (lambda L: sum(L) / max(1, len(L)))(

@@ -161,6 +161,30 @@ enum ea_option {
                                 (chi, d, chi) tensor (never shrunk), so that later updates up
                                 to bond chi need no new site memory, as the allocation-free
                                 entry point requires.  Allocates; EA_ENOMEM on failure. */
+    EA_OPT_TOPK = 17,        /* 1: a two-site update whose matrix X (Theta, or Theta^H when
+                                it is wider than tall; mw x nw, mw >= nw) has at least
+                                EA_OPT_TOPK_MIN columns takes a partial factorisation when
+                                a subspace of l = min(chi_max, 2 chi_m) + p columns (p =
+                                EA_OPT_TOPK_OVERSAMPLE) satisfies 4 l <= 3 nw: randomized
+                                subspace iteration in FP64 (Q = orth(X^H Omega), then q =
+                                EA_OPT_TOPK_POWER times Q = orth(X^H orth(X Q)); Omega from
+                                SplitMix64, seed EA_OPT_TOPK_SEED, counters from the gate
+                                index and attempt), shifted Cholesky QR for orth, the Jacobi
+                                SVD of X Q (mw x l) in the working precision, and the kept
+                                rank of Sec. VI from its singular values with every
+                                discarded weight raised by R = ||X||_F^2 - ||X Q||_F^2 (so
+                                f is the exact fidelity of the state kept).  Accepted when
+                                the kept rank is at most l - p, else l doubles; when 4 l >
+                                3 nw, or orth meets a rank-deficient block, the full
+                                factorisation runs.  Not in the paper (Sec. V takes the
+                                full SVD); k may exceed the full SVD's, and a capped update
+                                may keep less weight.  Off (0) by default; never used by
+                                forced ranks, the layer-parallel gauge, the small-bond
+                                launches or the allocation-free entry point. */
+    EA_OPT_TOPK_OVERSAMPLE = 18, /* p, 1..512 (default 32) */
+    EA_OPT_TOPK_POWER = 19,  /* q, 0..4 subspace iterations (default 1) */
+    EA_OPT_TOPK_SEED = 20,   /* seed of the start block, an integer in [0, 2^53) (default 0) */
+    EA_OPT_TOPK_MIN = 21,    /* smallest nw that tries the partial factorisation (default 256) */
     EA_OPT_QR_PRECOND = 12   /* w > 0: a factorisation of at least w columns on the
                                 three-kernel Jacobi first takes the Householder QR of its
                                 matrix (Theta = Q R, panels on one workgroup each, trailing
@@ -239,6 +263,10 @@ typedef struct ea_gate_record {
     int32_t k_f;     /* rank asked for by the target alone */
     int32_t sweeps;  /* Jacobi sweeps used */
     int32_t capped;  /* 1 if chi_max bound */
+    int32_t subspace;/* EA_OPT_TOPK: dimension l of the subspace the kept values came
+                        from; 0 for a full factorisation */
+    int32_t attempts;/* EA_OPT_TOPK: subspace attempts made (the last one accepted
+                        when subspace > 0); 0 when none was tried */
     double f_t;      /* target truncation fidelity */
     double f;        /* achieved truncation fidelity 1 - D(k)/T */
     double total;    /* T = sum of all s^2 */
@@ -450,8 +478,10 @@ enum ea_kfamily {
     EA_K_GEMM = 9,         /* absorb products (centre moves, chain contraction) */
     EA_K_OTHER = 10,
     EA_K_MOVE = 11,        /* whole centre moves (overlaps the families above) */
-    EA_K_QR = 12,          /* QR preconditioning: panels, trailing updates, Q products */
-    EA_K_COUNT = 13
+    EA_K_QR = 12,          /* QR: preconditioning panels and products, Cholesky QR passes */
+    EA_K_TOPK = 13,        /* partial factorisation: start block, range-finder products,
+                              the weight outside the subspace, right vectors */
+    EA_K_COUNT = 14
 };
 
 /* every >= 1: reset the counters and start counting every kernel launch of

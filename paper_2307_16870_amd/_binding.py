@@ -26,6 +26,8 @@ EA_OPT_JACOBI_TOL, EA_OPT_MAX_SWEEPS, EA_OPT_TAU, EA_OPT_BLOCK, EA_OPT_CHI_MAX =
 EA_OPT_INNER_SWEEPS, EA_OPT_JACOBI_KERNEL, EA_OPT_ROT_THREADS, EA_OPT_REORTH = 5, 6, 7, 8
 EA_OPT_JACOBI_ORDER, EA_OPT_SMALL_LAYERS, EA_OPT_JACOBI_SKIP, EA_OPT_QR_PRECOND = 9, 10, 11, 12
 EA_OPT_QR_MOVES, EA_OPT_RESERVE_BOND, EA_OPT_GAUGE, EA_OPT_GAUGE_PARALLEL = 13, 14, 15, 16
+EA_OPT_TOPK, EA_OPT_TOPK_OVERSAMPLE, EA_OPT_TOPK_POWER, EA_OPT_TOPK_SEED = 17, 18, 19, 20
+EA_OPT_TOPK_MIN = 21
 EA_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 SYMBOLS = [
@@ -45,10 +47,11 @@ SYMBOLS = [
 ETA_REL_DEFAULT = 1e-12
 
 K_FAMILY_NAMES = ["theta", "jacobi_gram", "jacobi_rot", "jacobi_apply", "jacobi_fused",
-                  "jacobi_small", "norms", "trunc", "gather", "gemm", "other", "centre_move", "qr"]
+                  "jacobi_small", "norms", "trunc", "gather", "gemm", "other", "centre_move", "qr",
+                  "topk"]
 (EA_K_THETA, EA_K_JGRAM, EA_K_JROT, EA_K_JAPPLY, EA_K_JFUSED, EA_K_JSMALL, EA_K_NORMS,
- EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_MOVE, EA_K_QR) = range(13)
-EA_K_COUNT = 13
+ EA_K_TRUNC, EA_K_GATHER, EA_K_GEMM, EA_K_OTHER, EA_K_MOVE, EA_K_QR, EA_K_TOPK) = range(14)
+EA_K_COUNT = 14
 
 
 class EAError(RuntimeError):
@@ -76,8 +79,9 @@ class GateRecord(ct.Structure):
     _fields_ = [("gate", ct.c_int64), ("site", ct.c_int32), ("chi_l", ct.c_int32),
                 ("chi_m", ct.c_int32), ("chi_r", ct.c_int32), ("k", ct.c_int32),
                 ("k_f", ct.c_int32), ("sweeps", ct.c_int32), ("capped", ct.c_int32),
-                ("f_t", ct.c_double), ("f", ct.c_double), ("total", ct.c_double),
-                ("lnP", ct.c_double), ("lnS", ct.c_double)]
+                ("subspace", ct.c_int32), ("attempts", ct.c_int32), ("f_t", ct.c_double),
+                ("f", ct.c_double), ("total", ct.c_double), ("lnP", ct.c_double),
+                ("lnS", ct.c_double)]
 
 
 _ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)

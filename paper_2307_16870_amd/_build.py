@@ -23,7 +23,7 @@ OBJDIR = os.path.join(PKG, "_build")
 LIBNAME = "libeamps.so"
 
 SOURCES = ["k_linalg.hip", "k_theta3.hip", "k_jacobi.hip", "k_jacobi2.hip", "k_observe.hip", "k_small.hip", "k_adjoint.hip",
-           "k_qr.hip", "k_zgemm.hip", "k_chol.hip", "k_vidal.hip", "ea_api.hip", "ea_adjoint.hip"]
+           "k_qr.hip", "k_zgemm.hip", "k_chol.hip", "k_vidal.hip", "k_topk.hip", "ea_api.hip", "ea_adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EA_OFFLOAD_ARCH", "gfx950")

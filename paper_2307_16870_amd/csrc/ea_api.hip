@@ -167,7 +167,8 @@ void mps_free(ea_mps *h) {
                       &h->stage_dev, &h->sm_scratch, &h->sm_sites, &h->sm_bond, &h->sm_loff, &h->sm_gsite,
                       &h->sm_gmat, &h->sm_budget, &h->sm_log, &h->sm_fout, &h->sm_descs,
                       &h->cq_x, &h->cq_q, &h->cq_g, &h->cq_r1, &h->cq_r2, &h->cq_ri, &h->cq_t,
-                      &h->cq_misc, &h->cbuf, &h->ybuf};
+                      &h->cq_misc, &h->cbuf, &h->ybuf, &h->tk_x, &h->tk_om, &h->tk_y,
+                      &h->tk_w, &h->tk_q1, &h->tk_vj, &h->tk_misc};
     for (DevBuf *b : bufs) free_buf(*b);
     for (auto &b : h->lam) free_buf(b);
     if (h->stage_host) (void)hipHostFree(h->stage_host);
@@ -244,6 +245,30 @@ int mps_set_option(ea_mps *h, int option, double value) {
         }
         return EA_OK;
     }
+    case EA_OPT_TOPK:
+        if (value != 0 && value != 1) return set_err(EA_EINVAL, "must be 0 or 1");
+        h->topk = value != 0;
+        return EA_OK;
+    case EA_OPT_TOPK_OVERSAMPLE:
+        if (!(value >= 1 && value <= 512) || value != std::floor(value))
+            return set_err(EA_EINVAL, "oversampling must be an integer in 1..512");
+        h->topk_p = (int)value;
+        return EA_OK;
+    case EA_OPT_TOPK_POWER:
+        if (!(value >= 0 && value <= 4) || value != std::floor(value))
+            return set_err(EA_EINVAL, "subspace iterations must be an integer in 0..4");
+        h->topk_q = (int)value;
+        return EA_OK;
+    case EA_OPT_TOPK_SEED:
+        if (!(value >= 0 && value < 9007199254740992.0) || value != std::floor(value))
+            return set_err(EA_EINVAL, "seed must be an integer in [0, 2^53)");
+        h->topk_seed = (unsigned long long)value;
+        return EA_OK;
+    case EA_OPT_TOPK_MIN:
+        if (!(value >= 2 && value <= EA_SORT_MAX) || value != std::floor(value))
+            return set_err(EA_EINVAL, "minimum width must be an integer in 2..4096");
+        h->topk_min = (int)value;
+        return EA_OK;
     case EA_OPT_GAUGE_PARALLEL:
         if (value != 0 && value != 1) return set_err(EA_EINVAL, "must be 0 or 1");
         h->vidal_parallel = value != 0;

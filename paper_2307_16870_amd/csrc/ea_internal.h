@@ -75,6 +75,12 @@ struct ea_mps {
     ea::DevBuf cq_x, cq_q, cq_g, cq_r1, cq_r2, cq_ri, cq_t, cq_misc;  // Cholesky QR workspace
     long n_chol_fallback = 0;  // Cholesky QR moves that fell back to the SVD move
     long n_cholqr_single = 0;  // Cholesky QR moves that needed one pass
+    long n_topk = 0, n_topk_fallback = 0;  // partial factorisations accepted / abandoned
+    // partial (top-k) factorisation of two-site updates (off by default)
+    bool topk = false;
+    int topk_p = 32, topk_q = 1, topk_min = 256;
+    unsigned long long topk_seed = 0;
+    ea::DevBuf tk_x, tk_om, tk_y, tk_w, tk_q1, tk_vj, tk_misc;
     // layer-parallel gauge (Vidal form, Hastings update): site tensors hold
     // B_i = Gamma_i Lambda_{i+1}; lam[b] the FP64 Schmidt values of bond b
     int gauge = 0;  // 0: one orthogonality centre; 1: layer-parallel
@@ -1000,6 +1006,179 @@ inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_ort
     return h->int_host[0] != 0 ? 1 : 0;
 }
 
+// Basis of range(Y), Y (rows x cols, column-major FP64, rows >= cols), by
+// shifted Cholesky QR: one pass on G + s I with s = 11 (rows cols + cols
+// (cols + 1)) 2^-53 trace(G) (trace(G) = ||Y||_F^2 bounds ||Y||_2^2), which
+// keeps the Cholesky factorisation defined however ill-conditioned Y is and
+// leaves a basis Q1 = Y R^{-1} of condition number below about 1e4; with
+// `full`, Cholesky QR2 on Q1 then makes it orthonormal to FP64 rounding
+// (Fukaya et al., SIAM J. Sci. Comput. 42, 2020).  The intermediate bases of
+// a subspace iteration need only span the right space, so they stop after
+// the shifted pass.  *Q points at the basis (rows x cols, column-major: tk_q1
+// after the shifted pass, cq_x when full).  Returns 1 when a pivot of the
+// full passes breaks down (Y numerically rank-deficient), 0 on success.
+inline int orth_cols(ea_mps *h, const double *Y, int rows, int cols, bool full,
+                     const double **Q) {
+    // in the row-major terms of cholqr2: Y is cols x rows with orthonormal rows
+    const int n = cols;
+    const size_t nx = (size_t)rows * cols, nn = (size_t)n * n;
+    TRY(ensure(h, h->cq_g, 16 * nn));
+    TRY(ensure(h, h->cq_r1, 16 * nn));
+    TRY(ensure(h, h->cq_ri, 16 * nn));
+    TRY(ensure(h, h->cq_t, 16 * nn));
+    TRY(ensure(h, h->cq_misc, 256 + 8 * (size_t)((n + 3) / 4)));
+    TRY(ensure(h, h->tk_q1, 16 * nx));
+    double *dmax = (double *)h->cq_misc.p;
+    int *flag = (int *)((char *)h->cq_misc.p + 64);
+    {
+        ProfScope ps(h, EA_K_QR, 8.0 * (double)nx * n * 2 + 8.0 * (double)nn * n,
+                     16.0 * (3.0 * nx + 3.0 * nn));
+        launch_zgemm<double>(0, 1, n, n, rows, 1.0, 0.0, Y, rows, Y, rows, 0.0, 0.0, h->cq_g.p, n,
+                             h->stream);
+        const double rel = 11.0 * ((double)rows * cols + (double)cols * (cols + 1)) *
+                           std::ldexp(1.0, -53);
+        launch_shift_diag(h->cq_g.p, n, rel, h->stream);
+        launch_cholesky_inv(h->cq_g.p, h->cq_r1.p, h->cq_ri.p, h->cq_t.p, n, dmax,
+                            CHOLQR_PIVOT_REL, flag, h->stream);
+        launch_zgemm<double>(1, 0, n, rows, n, 1.0, 0.0, h->cq_ri.p, n, Y, rows, 0.0, 0.0,
+                             h->tk_q1.p, rows, h->stream);
+    }
+    LAUNCHCHK(h);
+    *Q = (const double *)h->tk_q1.p;
+    if (!full) return 0;
+    const int rc = cholqr2(h, (const double *)h->tk_q1.p, n, rows, false, 1e-13);
+    *Q = (const double *)h->cq_x.p;
+    return rc;
+}
+
+// Partial (top-k) factorisation of X = W (mw x nw, column-major, mw >= nw,
+// working precision) for a two-site update across a bond of dimension chiM:
+// the reading taken and the acceptance rule are documented at EA_OPT_TOPK.
+// Every product of the range finder runs in FP64 on the matrix cores:
+//   T = ||X||_F^2;  Q = orth(X^H Omega);  q times Q = orth(X^H orth(X Q));
+//   W64 = X Q (mw x l);  R = max(0, T - ||W64||_F^2);
+// then the working-precision Jacobi SVD of W64 (W = U S, V_W), V = Q V_W, and
+// the kept rank from the columns' norms with every discarded weight raised by
+// R.  When an attempt is accepted, *used = l and W (mw x l), V (nw x l),
+// s_raw, perm, s_sorted and the record hold what factor_and_decide leaves
+// for a full factorisation; otherwise *used = 0 and W holds X again.
+// *attempts counts the subspaces tried.
+template <typename T>
+int topk_factor(ea_mps *h, int mw, int nw, int chiM, double f_t, int *used, int *attempts) {
+    *used = 0;
+    *attempts = 0;
+    const int p = h->topk_p;
+    const int cap = h->chi_max > 0 ? std::min(h->chi_max, nw) : nw;
+    long l = (long)std::min(cap, 2 * chiM) + p;
+    if (4 * l > 3 * (long)nw) return EA_OK;
+    const size_t nx = (size_t)mw * nw;
+    const size_t nparts = sumsq_part_doubles();
+    TRY(ensure(h, h->tk_x, 16 * nx));
+    TRY(ensure(h, h->tk_misc, 8 * (nparts + 8)));
+    TRY(ensure(h, h->s_raw, sizeof(double) * nw));
+    TRY(ensure(h, h->s_sorted, sizeof(double) * nw));
+    TRY(ensure(h, h->perm, sizeof(int) * nw));
+    double *sums = (double *)h->tk_misc.p;  // T, ||W64||^2, R
+    double *part = sums + 8;
+    const double *X = (const double *)h->tk_x.p;
+    {
+        ProfScope ps(h, EA_K_TOPK, 4.0 * (double)nx, (double)(h->csz + 16) * nx + 16.0 * nx);
+        launch_to_c128<T>(h->W.p, (double *)h->tk_x.p, nx, h->stream);
+        launch_sumsq(X, nx, part, sums, h->stream);
+    }
+    for (int a = 0; 4 * l <= 3 * (long)nw; ++a) {
+        const int L = (int)l;
+        *attempts = a + 1;
+        const size_t nml = (size_t)mw * L, nnl = (size_t)nw * L;
+        TRY(ensure(h, h->tk_om, 16 * nml));
+        TRY(ensure(h, h->tk_y, 16 * nnl));
+        TRY(ensure(h, h->tk_w, 16 * nml));
+        TRY(ensure(h, h->tk_vj, 16 * (size_t)L * L));
+        const unsigned long long base =
+            ((unsigned long long)((h->g & 0xFFFFF) * 16 + a)) << 40;
+        {
+            ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nml * nw, 16.0 * (nx + nml + nnl));
+            launch_omega(h->topk_seed, base, nml, (double *)h->tk_om.p, h->stream);
+            // Y = X^H Omega (nw x L)
+            TRY(blas_gemm<double>(h, 'C', 'N', nw, L, mw, 1.0, X, mw, h->tk_om.p, mw, 0.0,
+                                  h->tk_y.p, nw));
+        }
+        // Q = orth(Y); q times Q = orth(X^H orth(X Q)); only the last basis is
+        // made orthonormal, the others need only span the iterated subspace
+        const double *Q = nullptr;
+        int rc = orth_cols(h, (const double *)h->tk_y.p, nw, L, h->topk_q == 0, &Q);
+        for (int it = 0; rc == 0 && it < h->topk_q; ++it) {
+            {
+                ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nml * nw, 16.0 * (nx + nml + nnl));
+                // Z = X Q (mw x L)
+                TRY(blas_gemm<double>(h, 'N', 'N', mw, L, nw, 1.0, X, mw, Q, nw, 0.0,
+                                      h->tk_om.p, mw));
+            }
+            rc = orth_cols(h, (const double *)h->tk_om.p, mw, L, false, &Q);
+            if (rc != 0) break;
+            {
+                ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nml * nw, 16.0 * (nx + nml + nnl));
+                // Y = X^H Q' (nw x L)
+                TRY(blas_gemm<double>(h, 'C', 'N', nw, L, mw, 1.0, X, mw, Q, mw, 0.0,
+                                      h->tk_y.p, nw));
+            }
+            rc = orth_cols(h, (const double *)h->tk_y.p, nw, L, it + 1 == h->topk_q, &Q);
+        }
+        if (rc < 0) return rc;
+        if (rc == 1) {  // rank-deficient block: the full factorisation
+            h->n_topk_fallback += 1;
+            break;
+        }
+        // Q (nw x L, orthonormal, in cq_x) is kept until V = Q V_W
+        {
+            ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nml * nw + 4.0 * (double)nml,
+                         16.0 * (nx + 2.0 * nml + nnl) + (double)h->csz * nml);
+            // W64 = X Q (mw x L), R = T - ||W64||^2, W = W64 in the working precision
+            TRY(blas_gemm<double>(h, 'N', 'N', mw, L, nw, 1.0, X, mw, Q, nw, 0.0, h->tk_w.p,
+                                  mw));
+            launch_sumsq((const double *)h->tk_w.p, nml, part, sums + 1, h->stream);
+            launch_resid(sums, sums + 1, sums + 2, h->stream);
+            launch_from_c128<T>((const double *)h->tk_w.p, h->W.p, nml, h->stream);
+        }
+        TRY(svd_core<T>(h, mw, L));  // W = U S, V = V_W (L x L)
+        {
+            ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nnl * L,
+                         16.0 * (nnl * 2.0 + (double)L * L) + (double)h->csz * (nnl + (double)L * L));
+            // V = Q V_W (nw x L) in FP64, stored in the working precision
+            launch_to_c128<T>(h->V.p, (double *)h->tk_vj.p, (size_t)L * L, h->stream);
+            TRY(ensure(h, h->tk_q1, 16 * nnl));
+            TRY(blas_gemm<double>(h, 'N', 'N', nw, L, L, 1.0, Q, nw, h->tk_vj.p, L, 0.0,
+                                  h->tk_q1.p, nw));
+            launch_from_c128<T>((const double *)h->tk_q1.p, h->V.p, nnl, h->stream);
+        }
+        {
+            ProfScope ps(h, EA_K_NORMS, 4.0 * (double)nml, (double)h->csz * nml);
+            launch_colnorms<T>(h->W.p, mw, L, (double *)h->s_raw.p, h->stream);
+        }
+        {
+            ProfScope ps(h, EA_K_TRUNC, (double)L, 24.0 * L);
+            launch_sort_trunc((const double *)h->s_raw.p, L, f_t, h->chi_max, h->tau, 0, 0,
+                              (const int *)h->ints.p, (int *)h->perm.p, (double *)h->s_sorted.p,
+                              (ea_dev_rec *)h->rec.p, h->stream, sums + 2);
+        }
+        LAUNCHCHK(h);
+        HIPCHK(h, hipMemcpyAsync(h->rec_host, h->rec.p, sizeof(ea_dev_rec),
+                                 hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        prof_harvest(h);
+        if (h->rec_host->k <= L - p) {
+            *used = L;
+            h->n_topk += 1;
+            return EA_OK;
+        }
+        l = std::min<long>(nw, 2 * l);
+    }
+    // the full factorisation runs on X again
+    launch_from_c128<T>(X, h->W.p, nx, h->stream);
+    LAUNCHCHK(h);
+    return EA_OK;
+}
+
 // The site matrix of site c (n complex values) in FP64: the tensor itself
 // when T is double, else a converted copy in cq_x.
 template <typename T>
@@ -1151,7 +1330,10 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
                                  orient, h->stream);
     }
     LAUNCHCHK(h);
-    TRY(factor_and_decide<T>(h, mw, nw, f_t, 0, forced_k));
+    int sub = 0, att = 0;
+    if (h->topk && forced_k <= 0 && nw >= h->topk_min && h->arena == nullptr)
+        TRY(topk_factor<T>(h, mw, nw, chiM, f_t, &sub, &att));
+    if (sub == 0) TRY(factor_and_decide<T>(h, mw, nw, f_t, 0, forced_k));
     const ea_dev_rec rec = *h->rec_host;
     const int k = rec.k;
     if (!(rec.s0 > 0.0) || !std::isfinite(rec.total))
@@ -1187,6 +1369,8 @@ int apply_2q_impl(ea_mps *h, int i, const double *op, double budget, int dir, do
     r.k_f = rec.k_f;
     r.sweeps = rec.sweeps;
     r.capped = rec.capped;
+    r.subspace = sub;
+    r.attempts = att;
     r.f_t = f_t;
     r.f = rec.f;
     r.total = rec.total;
@@ -1302,6 +1486,8 @@ inline int vidal_finish(ea_mps *h, int i, const VidalOut &o, double *f_out) {
     r.k_f = rec.k_f;
     r.sweeps = rec.sweeps;
     r.capped = rec.capped;
+    r.subspace = 0;
+    r.attempts = 0;
     r.f_t = o.f_t;
     r.f = rec.f;
     r.total = rec.total;

@@ -119,10 +119,27 @@ void launch_fill_int(int *p, int n, int v, hipStream_t s);
 // ---- truncation -----------------------------------------------------------
 // mode 0: truncation rule of the two-site update; mode 1: centre move (keep
 // all numerically non-zero values, no renormalisation).  forced_k > 0 forces
-// the kept rank.  chi_max <= 0: no cap.
+// the kept rank.  chi_max <= 0: no cap.  resid (device, may be null): a
+// weight outside the r values (a partial factorisation) added to every
+// discarded weight and to T; k_f = r + 1 when no k <= r meets the target.
 void launch_sort_trunc(const double *s_raw, int r, double f_t, int chi_max, double tau,
                        int mode, int forced_k, const int *sweeps_dev, int *perm,
-                       double *s_sorted, ea_dev_rec *rec, hipStream_t s);
+                       double *s_sorted, ea_dev_rec *rec, hipStream_t s,
+                       const double *resid = nullptr);
+
+// ---- partial (top-k) factorisation ------------------------------------------
+// out[e] (n complex FP64) = (2u(base + 2e) - 1) + i (2u(base + 2e + 1) - 1),
+// u(x) the top 53 bits of SplitMix64(seed) at counter x times 2^-53.
+void launch_omega(unsigned long long seed, unsigned long long base, size_t n, double *out,
+                  hipStream_t s);
+// out[0] = sum of |x|^2 over n complex FP64 values (part: sumsq_part_doubles()
+// doubles of scratch); the same bits on every run.
+size_t sumsq_part_doubles();
+void launch_sumsq(const double *x, size_t n, double *part, double *out, hipStream_t s);
+// out[0] = max(0, a[0] - b[0]) on the device.
+void launch_resid(const double *a, const double *b, double *out, hipStream_t s);
+// G (n x n complex FP64): G_ii += rel * trace(G).
+void launch_shift_diag(void *G, int n, double rel, hipStream_t s);
 
 // ---- one-sided block Jacobi ----------------------------------------------
 // Single-workgroup form for n <= 64 columns: iterates to convergence.

@@ -39,77 +39,69 @@ __global__ __launch_bounds__(256) void k_chol_dmax(const cx<double> *__restrict_
 // R_jj^{-1}.  A pivot at or below rel_min * max diag(G) (or not finite)
 // marks a breakdown in *flag and is replaced by that bound, so that the
 // factorisation still completes with finite values (the host then discards
-// it).  One wave; lane t keeps column t of the block in registers (all loops
-// over the block's rows are unrolled, so the columns never leave registers);
-// per pivot step the pivot and then row p of R are broadcast through LDS.
+// it).  One wave; the block lives in LDS and lane l works on column
+// t = l % NB, the two lanes of a column splitting every sum by parity.  Row p
+// of R is formed left-looking, R[p][t] = (G[p][t] - sum_{k<p} conj(R[k][p])
+// R[k][t]) / R[p][p], so the inner loops only read LDS and their loads
+// overlap.  The loops stay rolled so that the code fits the instruction
+// cache (a fully unrolled, register-resident form ran six times slower).
 __global__ __launch_bounds__(64) void k_chol_diag(const cx<double> *__restrict__ G,
                                                   cx<double> *__restrict__ R,
                                                   cx<double> *__restrict__ Rinv, int n, int j0,
                                                   int nb, const double *__restrict__ dmax,
                                                   double rel_min, int *__restrict__ flag) {
-    __shared__ cx<double> S[NB][NB + 1];
-    __shared__ cx<double> rowp[NB];
+    static_assert(NB == 32, "two lanes per column of a 32-wide block");
+    __shared__ cx<double> S[NB][NB + 1];   // rows < p: R; rows >= p: G
+    __shared__ cx<double> Xi[NB][NB + 1];  // R_jj^{-1}, column c in Xi[.][c]
     __shared__ double piv;
-    const int t = threadIdx.x;
-    const bool own = t < nb;
-    cx<double> col[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        col[i] = (own && i < nb) ? G[(size_t)(j0 + i) * n + j0 + t] : zero_cx<double>();
+    const int l = threadIdx.x, t = l & (NB - 1), h = l >> 5;
+    for (int i = h; i < NB; i += 2)
+        S[i][t] = (i < nb && t < nb) ? G[(size_t)(j0 + i) * n + j0 + t] : zero_cx<double>();
+    __syncthreads();
     const double dmin = rel_min * *dmax;
-#pragma unroll
-    for (int p = 0; p < NB; ++p) {
-        if (p < nb) {
-            if (t == p) piv = col[p].x;
-            __syncthreads();
-            double dp = piv;
+    for (int p = 0; p < nb; ++p) {
+        cx<double> dot = zero_cx<double>();
+        if (t >= p && t < nb) {
+#pragma unroll 4
+            for (int k = h; k < p; k += 2) cmacc(dot, S[k][p], S[k][t]);
+        }
+        dot.x += __shfl_xor(dot.x, 32);
+        dot.y += __shfl_xor(dot.y, 32);
+        if (l == p) {
+            double dp = S[p][p].x - dot.x;
             if (!(dp > dmin)) {  // also catches NaN
-                if (t == 0) *flag = 1;
+                *flag = 1;
                 dp = dmin > 0.0 ? dmin : 1.0;
             }
-            const double rp = sqrt(dp), ir = 1.0 / rp;
-            // row p of R: R[p][t] = S[p][t] / r_p for t >= p
-            if (t == p) col[p] = mk<double>(rp, 0.0);
-            else if (t > p && own) col[p] = ir * col[p];
-            if (t > p && own) rowp[t] = col[p];
-            __syncthreads();
-            // trailing upper triangle: S[q][t] -= conj(R[p][q]) R[p][t], p < q <= t
-            if (t > p && own) {
-                const cx<double> b = col[p];
-#pragma unroll
-                for (int q = p + 1; q < NB; ++q) {
-                    if (q <= t) {
-                        const cx<double> a = rowp[q];
-                        cmacc(col[q], mk<double>(-a.x, -a.y), b);
-                    }
-                }
-            }
+            piv = sqrt(dp);
         }
+        __syncthreads();
+        const double rp = piv;
+        if (h == 0 && t >= p && t < nb)
+            S[p][t] = t == p ? mk<double>(rp, 0.0) : (1.0 / rp) * (S[p][t] - dot);
+        __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        if (own) S[i][t] = i <= t ? col[i] : zero_cx<double>();
-    __syncthreads();
-    // R_jj^{-1}, column c per lane: back substitution of R x = e_c
-    const int c = t;
-    cx<double> x[NB];
-#pragma unroll
-    for (int i = NB - 1; i >= 0; --i) {
-        x[i] = zero_cx<double>();
-        if (own && i < nb && i <= c) {
-            cx<double> acc = mk<double>(i == c ? 1.0 : 0.0, 0.0);
-#pragma unroll
-            for (int j = i + 1; j < NB; ++j)
-                if (j <= c) acc = acc - S[i][j] * x[j];
-            x[i] = (1.0 / S[i][i].x) * acc;
+    // R_jj^{-1}, column c = t: back substitution of R x = e_c, from the last
+    // row up; the sum over j > i is split by parity between the two lanes
+    for (int i = nb - 1; i >= 0; --i) {
+        cx<double> acc = zero_cx<double>();
+        if (t < nb && i < t) {
+#pragma unroll 4
+            for (int j = i + 1 + h; j <= t; j += 2) cmac(acc, S[i][j], Xi[j][t]);
         }
+        acc.x += __shfl_xor(acc.x, 32);
+        acc.y += __shfl_xor(acc.y, 32);
+        if (h == 0 && t < nb) {
+            const cx<double> rhs = mk<double>((i == t ? 1.0 : 0.0) - acc.x, -acc.y);
+            Xi[i][t] = i <= t ? (1.0 / S[i][i].x) * rhs : zero_cx<double>();
+        }
+        __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        if (own && i < nb) {
+    for (int i = h; i < nb; i += 2) {
+        if (t < nb) {
             const size_t o = (size_t)(j0 + i) * n + j0 + t;
-            R[o] = S[i][t];
-            Rinv[o] = x[i];
+            R[o] = i <= t ? S[i][t] : zero_cx<double>();
+            Rinv[o] = Xi[i][t];
         }
     }
 }

@@ -270,7 +270,8 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(const double *__restrict__ 
                                                      const int *__restrict__ sweeps_dev,
                                                      int *__restrict__ perm,
                                                      double *__restrict__ s_sorted,
-                                                     ea_dev_rec *__restrict__ rec) {
+                                                     ea_dev_rec *__restrict__ rec,
+                                                     const double *__restrict__ resid) {
     __shared__ double key[EA_SORT_MAX];
     __shared__ int idx[EA_SORT_MAX];
     __shared__ double Dsuf[EA_SORT_MAX + 1];
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(const double *__restrict__ 
         idx[i] = i;
     }
     if (tid == 0) {
-        kf_sh = r;
+        kf_sh = resid ? r + 1 : r;
         knz_sh = 0;
     }
     __syncthreads();
@@ -335,10 +336,15 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(const double *__restrict__ 
     }
     if (tid == 0) Dsuf[r] = 0.0;
     __syncthreads();
+    if (resid) {  // the weight outside a partial factorisation's subspace
+        const double R = *resid;
+        for (int i = tid; i <= r; i += nth) Dsuf[i] += R;
+        __syncthreads();
+    }
     const double T = Dsuf[0];
     const double s0 = r > 0 ? key[0] : 0.0;
     const double thr = (1.0 - f_t) * T;
-    int kmin = r;
+    int kmin = resid ? r + 1 : r;
     int cnt = 0;
     for (int k = tid + 1; k <= r; k += nth)
         if (Dsuf[k] <= thr && k < kmin) kmin = k;
@@ -386,9 +392,9 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(const double *__restrict__ 
 
 void launch_sort_trunc(const double *s_raw, int r, double f_t, int chi_max, double tau,
                        int mode, int forced_k, const int *sweeps_dev, int *perm,
-                       double *s_sorted, ea_dev_rec *rec, hipStream_t s) {
+                       double *s_sorted, ea_dev_rec *rec, hipStream_t s, const double *resid) {
     k_sort_trunc<<<1, 1024, 0, s>>>(s_raw, r, f_t, chi_max, tau, mode, forced_k, sweeps_dev,
-                                    perm, s_sorted, rec);
+                                    perm, s_sorted, rec, resid);
 }
 
 // ---------------------------------------------------------------------------

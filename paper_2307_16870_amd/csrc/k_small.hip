@@ -70,7 +70,7 @@ __device__ double schedule_target_dev(int has_sched, int strategy, double f_min,
 // D(k) from the smallest value up, and the kept rank: mode 0 the update rule
 // k = min(k_f, k_nz, chi_max), mode 1 (centre move) k = k_nz.
 template <typename T>
-__device__ void factor(const SmallDesc<T> &D, const Work<T> &w, int m, int n, int mode,
+__device__ __noinline__ void factor(const SmallDesc<T> &D, const Work<T> &w, int m, int n, int mode,
                        double f_t, Dec &dec, double *s_raw, double *s_sorted, int *perm,
                        double *Dsuf, double *part, int *sw, int *cnt) {
     const int tid = threadIdx.x;
@@ -466,6 +466,8 @@ __global__ __launch_bounds__(NTH) void k_layer_small(SmallDesc<T> *descs) {
                 r.k_f = dec.k_f;
                 r.sweeps = dec.sweeps;
                 r.capped = dec.capped;
+                r.subspace = 0;
+                r.attempts = 0;
                 r.f_t = f_t;
                 r.f = dec.f;
                 r.total = dec.total;
