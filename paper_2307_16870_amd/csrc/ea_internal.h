@@ -1012,15 +1012,23 @@ inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_ort
 // keeps the Cholesky factorisation defined however ill-conditioned Y is and
 // leaves a basis Q1 = Y R^{-1} of condition number below about 1e4; with
 // `full`, Cholesky QR2 on Q1 then makes it orthonormal to FP64 rounding
-// (Fukaya et al., SIAM J. Sci. Comput. 42, 2020).  The intermediate bases of
-// a subspace iteration need only span the right space, so they stop after
-// the shifted pass.  *Q points at the basis (rows x cols, column-major: tk_q1
+// (Fukaya et al., SIAM J. Sci. Comput. 42, 2020); a full basis first tries
+// Cholesky QR2 without the shift.  The intermediate bases of a subspace
+// iteration need only span the right space, so they stop after the shifted
+// pass.  *Q points at the basis (rows x cols, column-major: tk_q1
 // after the shifted pass, cq_x when full).  Returns 1 when a pivot of the
 // full passes breaks down (Y numerically rank-deficient), 0 on success.
 inline int orth_cols(ea_mps *h, const double *Y, int rows, int cols, bool full,
                      const double **Q) {
     // in the row-major terms of cholqr2: Y is cols x rows with orthonormal rows
     const int n = cols;
+    if (full) {
+        // a Y of condition number below about 1e7 needs no shift: Cholesky
+        // QR2 directly (the shifted route only when a pivot breaks down)
+        const int rc = cholqr2(h, Y, n, rows, false, 1e-13);
+        *Q = (const double *)h->cq_x.p;
+        if (rc <= 0) return rc;
+    }
     const size_t nx = (size_t)rows * cols, nn = (size_t)n * n;
     TRY(ensure(h, h->cq_g, 16 * nn));
     TRY(ensure(h, h->cq_r1, 16 * nn));
