@@ -314,6 +314,7 @@ def bench_mpo40(args, torch, C, P):
     st = P.EAState(prog.n_sites, "mixed", args.prec, chi_max=cfg["chi_max"], stream=stream)
     if args.topk:
         st.set_option(P.EA_OPT_TOPK, 1)
+        st.set_option(P.EA_OPT_TOPK_POWER, args.topk_power)
     tiny = C.config_program(3, depth=2)[0]
     run_circuit(st, tiny, 1.0)
     torch.cuda.synchronize()
@@ -609,6 +610,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--topk", action="store_true",
                     help="partial (top-k) factorisation of eligible updates (EA_OPT_TOPK)")
+    ap.add_argument("--topk-power", type=int, default=1,
+                    help="subspace iterations of the partial factorisation (EA_OPT_TOPK_POWER)")
     ap.add_argument("--no-topk-variant", action="store_true",
                     help="skip the untimed run of the circuit with the partial factorisation")
     ap.add_argument("--cpu-layers", type=int, default=10)
@@ -669,6 +672,7 @@ def main():
     st = P.EAState(prog.n_sites, "pure", args.prec, chi_max=chi_max, stream=stream)
     if args.topk:
         st.set_option(P.EA_OPT_TOPK, 1)
+        st.set_option(P.EA_OPT_TOPK_POWER, args.topk_power)
     # load the kernels' code objects before anything is timed (not a step)
     tiny = C.brickwork_program(prog.n_sites, 2, 99)
     run_circuit(st, tiny, 1.0)
@@ -793,6 +797,7 @@ def main():
         log("partial-factorisation variant")
         stk = P.EAState(prog.n_sites, "pure", args.prec, chi_max=chi_max, stream=stream)
         stk.set_option(P.EA_OPT_TOPK, 1)
+        stk.set_option(P.EA_OPT_TOPK_POWER, args.topk_power)
         run_circuit(stk, tiny, 1.0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -802,7 +807,7 @@ def main():
         Fk, _ = stk.fidelity_estimate()
         gk = stk.gate_log()[-prog.n_2q:]
         out["topk_variant"] = {
-            "option": "EA_OPT_TOPK (oversampling 32, one subspace iteration)",
+            "option": f"EA_OPT_TOPK (oversampling 32, {args.topk_power} subspace iteration(s))",
             "ms_per_step": 1000 * tk, "updates_per_s": prog.n_2q / tk,
             "final_fidelity_estimate": Fk,
             "capped_updates": int(sum(r["capped"] for r in gk)),

@@ -166,10 +166,11 @@ enum ea_option {
                                 EA_OPT_TOPK_MIN columns takes a partial factorisation when
                                 a subspace of l = min(chi_max, 2 chi_m) + p columns (p =
                                 EA_OPT_TOPK_OVERSAMPLE) satisfies 4 l <= 3 nw: randomized
-                                subspace iteration in FP64 (Q = orth(X^H Omega), then q =
-                                EA_OPT_TOPK_POWER times Q = orth(X^H orth(X Q)); Omega from
+                                subspace iteration in FP64 (Y = X^H Omega, then q =
+                                EA_OPT_TOPK_POWER times Y = X^H (X Y), Q = orth(Y) by
+                                Cholesky QR2, shifted first if ill-conditioned; Omega from
                                 SplitMix64, seed EA_OPT_TOPK_SEED, counters from the gate
-                                index and attempt), shifted Cholesky QR for orth, the Jacobi
+                                index and attempt), the Jacobi
                                 SVD of X Q (mw x l) in the working precision, and the kept
                                 rank of Sec. VI from its singular values with every
                                 discarded weight raised by R = ||X||_F^2 - ||X Q||_F^2 (so

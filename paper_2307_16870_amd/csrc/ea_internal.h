@@ -1006,35 +1006,23 @@ inline int cholqr2(ea_mps *h, const double *X, int rows, int cols, bool cols_ort
     return h->int_host[0] != 0 ? 1 : 0;
 }
 
-// Basis of range(Y), Y (rows x cols, column-major FP64, rows >= cols), by
-// shifted Cholesky QR: one pass on G + s I with s = 11 (rows cols + cols
-// (cols + 1)) 2^-53 trace(G) (trace(G) = ||Y||_F^2 bounds ||Y||_2^2), which
-// keeps the Cholesky factorisation defined however ill-conditioned Y is and
-// leaves a basis Q1 = Y R^{-1} of condition number below about 1e4; with
-// `full`, Cholesky QR2 on Q1 then makes it orthonormal to FP64 rounding
-// (Fukaya et al., SIAM J. Sci. Comput. 42, 2020); a full basis first tries
-// Cholesky QR2 without the shift.  The intermediate bases of a subspace
-// iteration need only span the right space, so they stop after the shifted
-// pass.  *Q points at the basis (rows x cols, column-major: tk_q1
-// after the shifted pass, cq_x when full).  Returns 1 when a pivot of the
-// full passes breaks down (Y numerically rank-deficient), 0 on success.
-inline int orth_cols(ea_mps *h, const double *Y, int rows, int cols, bool full,
-                     const double **Q) {
+// Orthonormal basis of range(Y), Y (rows x cols, column-major FP64, rows >=
+// cols): Cholesky QR2 when Y's condition number is below about 1e7; when a
+// pivot breaks down, shifted Cholesky QR first (one pass on G + s I with
+// s = 11 (rows cols + cols (cols + 1)) 2^-53 trace(G), trace(G) = ||Y||_F^2
+// bounding ||Y||_2^2, which keeps the factorisation defined however
+// ill-conditioned Y is and leaves a basis of condition number below about
+// 1e4), then Cholesky QR2 on that (Fukaya et al., SIAM J. Sci. Comput. 42,
+// 2020).  *Q points at the basis (rows x cols, column-major, in cq_x).
+// Returns 1 when a pivot still breaks down (Y numerically rank-deficient),
+// 0 on success.
+inline int orth_cols(ea_mps *h, const double *Y, int rows, int cols, const double **Q) {
     // in the row-major terms of cholqr2: Y is cols x rows with orthonormal rows
     const int n = cols;
-    if (full) {
-        // a Y of condition number below about 1e7 needs no shift: Cholesky
-        // QR2 directly (the shifted route only when a pivot breaks down)
-        const int rc = cholqr2(h, Y, n, rows, false, 1e-13);
-        *Q = (const double *)h->cq_x.p;
-        if (rc <= 0) return rc;
-    }
     const size_t nx = (size_t)rows * cols, nn = (size_t)n * n;
-    TRY(ensure(h, h->cq_g, 16 * nn));
-    TRY(ensure(h, h->cq_r1, 16 * nn));
-    TRY(ensure(h, h->cq_ri, 16 * nn));
-    TRY(ensure(h, h->cq_t, 16 * nn));
-    TRY(ensure(h, h->cq_misc, 256 + 8 * (size_t)((n + 3) / 4)));
+    int rc = cholqr2(h, Y, n, rows, false, 1e-13);  // ensures the cq_* workspace
+    *Q = (const double *)h->cq_x.p;
+    if (rc <= 0) return rc;
     TRY(ensure(h, h->tk_q1, 16 * nx));
     double *dmax = (double *)h->cq_misc.p;
     int *flag = (int *)((char *)h->cq_misc.p + 64);
@@ -1052,9 +1040,7 @@ inline int orth_cols(ea_mps *h, const double *Y, int rows, int cols, bool full,
                              h->tk_q1.p, rows, h->stream);
     }
     LAUNCHCHK(h);
-    *Q = (const double *)h->tk_q1.p;
-    if (!full) return 0;
-    const int rc = cholqr2(h, (const double *)h->tk_q1.p, n, rows, false, 1e-13);
+    rc = cholqr2(h, (const double *)h->tk_q1.p, n, rows, false, 1e-13);
     *Q = (const double *)h->cq_x.p;
     return rc;
 }
@@ -1063,7 +1049,7 @@ inline int orth_cols(ea_mps *h, const double *Y, int rows, int cols, bool full,
 // working precision) for a two-site update across a bond of dimension chiM:
 // the reading taken and the acceptance rule are documented at EA_OPT_TOPK.
 // Every product of the range finder runs in FP64 on the matrix cores:
-//   T = ||X||_F^2;  Q = orth(X^H Omega);  q times Q = orth(X^H orth(X Q));
+//   T = ||X||_F^2;  Y = X^H Omega;  q times Y = X^H (X Y);  Q = orth(Y);
 //   W64 = X Q (mw x l);  R = max(0, T - ||W64||_F^2);
 // then the working-precision Jacobi SVD of W64 (W = U S, V_W), V = Q V_W, and
 // the kept rank from the columns' norms with every discarded weight raised by
@@ -1111,27 +1097,21 @@ int topk_factor(ea_mps *h, int mw, int nw, int chiM, double f_t, int *used, int 
             TRY(blas_gemm<double>(h, 'C', 'N', nw, L, mw, 1.0, X, mw, h->tk_om.p, mw, 0.0,
                                   h->tk_y.p, nw));
         }
-        // Q = orth(Y); q times Q = orth(X^H orth(X Q)); only the last basis is
-        // made orthonormal, the others need only span the iterated subspace
-        const double *Q = nullptr;
-        int rc = orth_cols(h, (const double *)h->tk_y.p, nw, L, h->topk_q == 0, &Q);
-        for (int it = 0; rc == 0 && it < h->topk_q; ++it) {
-            {
-                ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nml * nw, 16.0 * (nx + nml + nnl));
-                // Z = X Q (mw x L)
-                TRY(blas_gemm<double>(h, 'N', 'N', mw, L, nw, 1.0, X, mw, Q, nw, 0.0,
-                                      h->tk_om.p, mw));
-            }
-            rc = orth_cols(h, (const double *)h->tk_om.p, mw, L, false, &Q);
-            if (rc != 0) break;
-            {
-                ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nml * nw, 16.0 * (nx + nml + nnl));
-                // Y = X^H Q' (nw x L)
-                TRY(blas_gemm<double>(h, 'C', 'N', nw, L, mw, 1.0, X, mw, Q, mw, 0.0,
-                                      h->tk_y.p, nw));
-            }
-            rc = orth_cols(h, (const double *)h->tk_y.p, nw, L, it + 1 == h->topk_q, &Q);
+        // q times Y <- X^H (X Y), then Q = orth(Y): the power scheme spans the
+        // same subspace as orthonormalising after every product; in FP64 the
+        // growth of Y's condition number, (s_0 / s_L)^(2q+1), is left to the
+        // shifted Cholesky QR, and a block it cannot resolve falls back to
+        // the full factorisation
+        for (int it = 0; it < h->topk_q; ++it) {
+            ProfScope ps(h, EA_K_TOPK, 16.0 * (double)nml * nw, 16.0 * (2.0 * nx + 2.0 * nml + 2.0 * nnl));
+            // Z = X Y (mw x L), Y = X^H Z (nw x L)
+            TRY(blas_gemm<double>(h, 'N', 'N', mw, L, nw, 1.0, X, mw, h->tk_y.p, nw, 0.0,
+                                  h->tk_om.p, mw));
+            TRY(blas_gemm<double>(h, 'C', 'N', nw, L, mw, 1.0, X, mw, h->tk_om.p, mw, 0.0,
+                                  h->tk_y.p, nw));
         }
+        const double *Q = nullptr;
+        const int rc = orth_cols(h, (const double *)h->tk_y.p, nw, L, &Q);
         if (rc < 0) return rc;
         if (rc == 1) {  // rank-deficient block: the full factorisation
             h->n_topk_fallback += 1;
