@@ -246,6 +246,10 @@ def bench_batched(args, torch, C, P):
     n_upd = sum(p.n_2q for p in progs)
 
     states = [P.EAState(p.n_sites, "pure", args.prec, chi_max=1024) for p in progs]
+    if args.topk:
+        for st in states:
+            st.set_option(P.EA_OPT_TOPK, 1)
+            st.set_option(P.EA_OPT_TOPK_POWER, args.topk_power)
     depth = max(len(p.layers) for p in progs)
 
     graph = P.capture_batched(states, progs)
@@ -291,12 +295,15 @@ def bench_batched(args, torch, C, P):
         "vs_baseline": None, "dtype": "f64" if args.prec == "c128" else "f32",
         "data": "synthetic",
         "config": {"workload": f"batched-{len(progs)}-circuits-N20to80-depth<= {args.max_depth}",
-                   "circuits": len(progs), "updates": n_upd, "f_min": 0.99, "chi_max": 1024},
+                   "circuits": len(progs), "updates": n_upd, "f_min": 0.99, "chi_max": 1024,
+                   **({"topk": True} if args.topk else {})},
         "sequential_updates_per_s": None if ts is None else n_upd / ts,
         "speedup_batched_vs_sequential": None if ts is None else ts / tb,
         "circuits_with_P_ge_0.99": int(sum(F >= 0.99 for F in Fs)),
         "final_fidelity_estimates": [round(F, 6) for F in Fs],
         "capped_updates": int(sum(sum(r["capped"] for r in s.gate_log()) for s in states)),
+        "partial_factorisations": int(sum(sum(r["subspace"] > 0 for r in s.gate_log())
+                                          for s in states)),
         "first_pass_includes_code_loading": bool(args.single_pass),
     }
     graph.close()
