@@ -755,6 +755,8 @@ def main():
                        "below F_min" if F < f_min else "estimate at or above F_min"),
         "max_bond": int(max(st.bond_dims())),
         "partial_factorisations": int(sum(r["subspace"] > 0 for r in glog_full)),
+        "partial_attempts_not_accepted": int(sum(r["attempts"] > (1 if r["subspace"] else 0)
+                                                 for r in glog_full)),
         "jacobi_sweeps": {
             "mean": sum(r["sweeps"] for r in glog_full) / max(1, len(glog_full)),
             "mean_at_width_ge_1024": (lambda L: sum(L) / max(1, len(L)))(
@@ -814,11 +816,13 @@ def main():
         Fk, _ = stk.fidelity_estimate()
         gk = stk.gate_log()[-prog.n_2q:]
         out["topk_variant"] = {
-            "option": f"EA_OPT_TOPK (oversampling 32, {args.topk_power} subspace iteration(s))",
+            "option": f"EA_OPT_TOPK (oversampling 64, {args.topk_power} subspace iteration(s))",
             "ms_per_step": 1000 * tk, "updates_per_s": prog.n_2q / tk,
             "final_fidelity_estimate": Fk,
             "capped_updates": int(sum(r["capped"] for r in gk)),
             "partial_factorisations": int(sum(r["subspace"] > 0 for r in gk)),
+            "partial_attempts_not_accepted": int(sum(r["attempts"] > (1 if r["subspace"] else 0)
+                                                     for r in gk)),
             "speedup_vs_full_svd": tk and (ms_step / 1000.0) / tk}
         stk.close()
     st.close()

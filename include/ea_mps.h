@@ -182,7 +182,7 @@ enum ea_option {
                                 may keep less weight.  Off (0) by default; never used by
                                 forced ranks, the layer-parallel gauge, the small-bond
                                 launches or the allocation-free entry point. */
-    EA_OPT_TOPK_OVERSAMPLE = 18, /* p, 1..512 (default 32) */
+    EA_OPT_TOPK_OVERSAMPLE = 18, /* p, 1..512 (default 64) */
     EA_OPT_TOPK_POWER = 19,  /* q, 0..4 subspace iterations (default 1) */
     EA_OPT_TOPK_SEED = 20,   /* seed of the start block, an integer in [0, 2^53) (default 0) */
     EA_OPT_TOPK_MIN = 21,    /* smallest nw that tries the partial factorisation (default 256) */

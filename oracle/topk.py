@@ -136,7 +136,7 @@ def start_size(nw: int, chi_m: int, chi_max: Optional[int], p: int) -> int:
 
 
 def topk_factor(X: np.ndarray, f_t: float, chi_max: Optional[int], tau: float, chi_m: int,
-                p: int = 32, q: int = 1, seed: int = 0, gate: int = 0,
+                p: int = 64, q: int = 1, seed: int = 0, gate: int = 0,
                 svd: str = "auto") -> Optional[TopkResult]:
     """The accepted attempt for X (mw x nw, mw >= nw), or None when the full
     factorisation is to run (subspace too large for a gain)."""
@@ -168,7 +168,7 @@ class OracleTopK(OracleMPS):
 
     def __init__(self, n_sites: int, kind: str = "pure", chi_max: Optional[int] = None,
                  tau: float = 1e-13, svd: str = "auto", keep_spectra: bool = False,
-                 p: int = 32, q: int = 1, seed: int = 0, topk_min: int = 256):
+                 p: int = 64, q: int = 1, seed: int = 0, topk_min: int = 256):
         super().__init__(n_sites, kind, chi_max=chi_max, tau=tau, svd=svd,
                          keep_spectra=keep_spectra)
         self.p, self.q, self.seed, self.topk_min = p, q, seed, topk_min

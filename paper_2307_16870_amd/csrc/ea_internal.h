@@ -78,7 +78,7 @@ struct ea_mps {
     long n_topk = 0, n_topk_fallback = 0;  // partial factorisations accepted / abandoned
     // partial (top-k) factorisation of two-site updates (off by default)
     bool topk = false;
-    int topk_p = 32, topk_q = 1, topk_min = 256;
+    int topk_p = 64, topk_q = 1, topk_min = 256;
     unsigned long long topk_seed = 0;
     ea::DevBuf tk_x, tk_om, tk_y, tk_w, tk_q1, tk_vj, tk_misc;
     // layer-parallel gauge (Vidal form, Hastings update): site tensors hold
