@@ -1103,7 +1103,8 @@ int topk_factor(ea_mps *h, int mw, int nw, int chiM, double f_t, int *used, int 
         // shifted Cholesky QR, and a block it cannot resolve falls back to
         // the full factorisation
         for (int it = 0; it < h->topk_q; ++it) {
-            ProfScope ps(h, EA_K_TOPK, 16.0 * (double)nml * nw, 16.0 * (2.0 * nx + 2.0 * nml + 2.0 * nnl));
+            ProfScope ps(h, EA_K_TOPK, 16.0 * (double)nml * nw,
+                         16.0 * (2.0 * nx + 2.0 * nml + 2.0 * nnl));
             // Z = X Y (mw x L), Y = X^H Z (nw x L)
             TRY(blas_gemm<double>(h, 'N', 'N', mw, L, nw, 1.0, X, mw, h->tk_y.p, nw, 0.0,
                                   h->tk_om.p, mw));
@@ -1131,7 +1132,8 @@ int topk_factor(ea_mps *h, int mw, int nw, int chiM, double f_t, int *used, int 
         TRY(svd_core<T>(h, mw, L));  // W = U S, V = V_W (L x L)
         {
             ProfScope ps(h, EA_K_TOPK, 8.0 * (double)nnl * L,
-                         16.0 * (nnl * 2.0 + (double)L * L) + (double)h->csz * (nnl + (double)L * L));
+                         16.0 * (nnl * 2.0 + (double)L * L) +
+                             (double)h->csz * (nnl + (double)L * L));
             // V = Q V_W (nw x L) in FP64, stored in the working precision
             launch_to_c128<T>(h->V.p, (double *)h->tk_vj.p, (size_t)L * L, h->stream);
             TRY(ensure(h, h->tk_q1, 16 * nnl));
