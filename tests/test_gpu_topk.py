@@ -231,3 +231,36 @@ def test_options_checked_and_off_by_default():
                 st.set_option(opt, bad)
         st.apply_2q(1, C.haar_unitary(np.random.default_rng(0)), 1.0)
         assert st.gate_log()[0]["subspace"] == 0 and st.gate_log()[0]["attempts"] == 0
+
+
+def test_full_size_mpo_capped_update_fp32():
+    """The largest partial factorisation of the workloads: an MPO update at
+    chi = 1024, d = 4 (Theta 4096 x 4096, the 40-qubit noisy circuit's capped
+    updates), default oversampling: l = 1088 of 4096 columns.  Against the
+    oracle's partial mode (LAPACK SVD step): kept rank, f within 1e-5, the
+    kept values within FP32 bounds; the left site is an isometry."""
+    _say("case: topk full size MPO chi=1024 c64")
+    chi, d, f_t = 1024, 4, 1 - 8.77e-4
+    tens = C.random_mps_tensors([1, chi, chi, chi, 1], d, seed=4097)
+    u = C.haar_unitary(np.random.default_rng(4097))
+    G = C.depolarizing2_superop(1e-3) @ C.unitary_superop(u)
+    t = K.OracleTopK(4, "mixed", chi_max=chi, seed=0, topk_min=256, svd="lapack",
+                     keep_spectra=True)
+    t.load([a.copy() for a in tens], 1)
+    rec = t.apply_2q(1, G, f_t)
+    assert rec.subspace == 1088 and rec.capped and rec.k == chi
+    with P.EAState(4, "mixed", "c64", chi_max=chi) as st:
+        st.set_option(P.EA_OPT_TOPK, 1)
+        st.load(tens, 1)
+        st.apply_2q(1, G, f_t)
+        g = st.gate_log()[0]
+        a1, a2 = st.site(1), st.site(2)
+    assert g["subspace"] == 1088 and g["attempts"] == 1
+    assert g["k"] == rec.k and g["capped"]
+    assert abs(g["f"] - rec.f) < 1e-5
+    k = rec.k
+    sig = math.sqrt(float(np.sum(rec.s[:k] ** 2)))
+    got_s = np.linalg.norm(a2.reshape(k, -1), axis=1)
+    assert np.abs(got_s - rec.s[:k] / sig).max() < 1e-4 * rec.s[0] / sig
+    q = a1.reshape(-1, k)
+    assert np.abs(q.conj().T @ q - np.eye(k)).max() < 1e-5
