@@ -620,7 +620,8 @@ def main():
     ap.add_argument("--topk-power", type=int, default=1,
                     help="subspace iterations of the partial factorisation (EA_OPT_TOPK_POWER)")
     ap.add_argument("--no-topk-variant", action="store_true",
-                    help="skip the untimed run of the circuit with the partial factorisation")
+                    help="skip the untimed runs of the circuit with the partial factorisation "
+                         "and in the layer-parallel gauge")
     ap.add_argument("--cpu-layers", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--workload", default="brickwork50",
@@ -825,6 +826,25 @@ def main():
                                                      for r in gk)),
             "speedup_vs_full_svd": tk and (ms_step / 1000.0) / tk}
         stk.close()
+    if not args.no_topk_variant:
+        # the same circuit in the layer-parallel gauge (Vidal form, Hastings
+        # update): another variant beside the contract's number
+        log("layer-parallel variant")
+        stg = P.EAState(prog.n_sites, "pure", args.prec, chi_max=chi_max, stream=stream)
+        stg.set_option(P.EA_OPT_GAUGE, 1)
+        run_circuit(stg, tiny, 1.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_circuit(stg, prog, f_min, progress=True)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t1
+        Fg, _ = stg.fidelity_estimate()
+        out["layer_parallel_variant"] = {
+            "option": "EA_OPT_GAUGE (Vidal form, a layer's gates side by side; the estimate "
+                      "is approximate after truncations)",
+            "ms_per_step": 1000 * tg, "updates_per_s": prog.n_2q / tg,
+            "final_fidelity_estimate": Fg, "speedup_vs_full_svd": (ms_step / 1000.0) / tg}
+        stg.close()
     st.close()
     if not args.no_cpu:
         # the GPU on the oracle's sample: the first cpu_layers layers
