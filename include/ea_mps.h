@@ -183,7 +183,10 @@ enum ea_option {
                                 forced ranks, the layer-parallel gauge, the small-bond
                                 launches or the allocation-free entry point. */
     EA_OPT_TOPK_OVERSAMPLE = 18, /* p, 1..512 (default 64) */
-    EA_OPT_TOPK_POWER = 19,  /* q, 0..4 subspace iterations (default 1) */
+    EA_OPT_TOPK_POWER = 19,  /* q, 0..4 subspace iterations (default 1); Y's condition
+                                number grows as (s_0 / s_l)^(2q+1), and a block that the
+                                shifted Cholesky QR cannot resolve takes the full
+                                factorisation */
     EA_OPT_TOPK_SEED = 20,   /* seed of the start block, an integer in [0, 2^53) (default 0) */
     EA_OPT_TOPK_MIN = 21,    /* smallest nw that tries the partial factorisation (default 256) */
     EA_OPT_QR_PRECOND = 12   /* w > 0: a factorisation of at least w columns on the
