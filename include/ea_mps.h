@@ -181,7 +181,8 @@ enum ea_option {
                                 full SVD); k may exceed the full SVD's, and a capped update
                                 may keep less weight.  Off (0) by default; never used by
                                 forced ranks, the layer-parallel gauge, the small-bond
-                                launches or the allocation-free entry point. */
+                                launches, gradients (mps_energy_grad differentiates the
+                                full factorisation) or the allocation-free entry point. */
     EA_OPT_TOPK_OVERSAMPLE = 18, /* p, 1..512 (default 64) */
     EA_OPT_TOPK_POWER = 19,  /* q, 0..4 subspace iterations (default 1); Y's condition
                                 number grows as (s_0 / s_l)^(2q+1), and a block that the

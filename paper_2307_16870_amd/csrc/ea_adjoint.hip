@@ -713,6 +713,14 @@ extern "C" int mps_energy_grad(ea_mps *h, int n_ops, const ea_dop *ops, const do
         nop += widths[t] == 1 ? 4 : 16;
     }
     if (!finite_cplx(term_ops, nop)) return set_err(EA_EINVAL, "non-finite term operator");
+    // the adjoint differentiates the full factorisation of every update: the
+    // partial one is off for the call and restored after it
+    struct TopkOff {
+        ea_mps *h;
+        bool saved;
+        ~TopkOff() { h->topk = saved; }
+    } topk_off{h, h->topk};
+    h->topk = false;
     return h->f64 ? energy_grad_impl<double>(h, n_ops, ops, params, n_params, n_terms, sites,
                                              widths, term_ops, coefs, f_min, eta_rel, E_out,
                                              grad_out, lnP_out)

@@ -264,3 +264,29 @@ def test_full_size_mpo_capped_update_fp32():
     assert np.abs(got_s - rec.s[:k] / sig).max() < 1e-4 * rec.s[0] / sig
     q = a1.reshape(-1, k)
     assert np.abs(q.conj().T @ q - np.eye(k)).max() < 1e-5
+
+
+def test_gradients_take_the_full_factorisation():
+    """mps_energy_grad differentiates the full factorisation: with the
+    partial one switched on (and eligible from 8 columns) the energy, the
+    gradient and ln P are bit-identical to a run without it, and the option
+    is still on afterwards."""
+    _say("case: topk off for gradients")
+    n, L = 12, 4
+    angles = C.hea_angles(n, L, seed=9)
+    terms = C.hea_hamiltonian(n)
+    res = []
+    for on in (0, 1):
+        with P.EAState(n, "pure", "c64") as st:
+            if on:
+                _options(st, 4, 1, 0, 8)
+            res.append(P.mps_energy_grad(st.h, P.hea_dops(n, L), angles, terms,
+                                         f_min=0.99))
+            if on:  # the option survives the call: a circuit then takes it
+                st.reset()
+                st.set_option(P.EA_OPT_CHI_MAX, 8)
+                st.set_option(P.EA_OPT_SMALL_LAYERS, 0)
+                st.run(C.brickwork_program(n, 10, 21), 0.95)
+                assert any(g["subspace"] > 0 for g in st.gate_log())
+    (E0, g0, l0), (E1, g1, l1) = res
+    assert E0 == E1 and l0 == l1 and np.array_equal(g0, g1)
