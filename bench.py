@@ -619,7 +619,7 @@ def main():
                     help="partial (top-k) factorisation of eligible updates (EA_OPT_TOPK)")
     ap.add_argument("--topk-power", type=int, default=1,
                     help="subspace iterations of the partial factorisation (EA_OPT_TOPK_POWER)")
-    ap.add_argument("--no-topk-variant", action="store_true",
+    ap.add_argument("--no-variants", "--no-topk-variant", dest="no_variants", action="store_true",
                     help="skip the untimed runs of the circuit with the partial factorisation "
                          "and in the layer-parallel gauge")
     ap.add_argument("--cpu-layers", type=int, default=10)
@@ -801,7 +801,7 @@ def main():
                        "final_fidelity_estimate": F64,
                        "speedup_mixed_vs_fp64": t64 / (ms_step / 1000.0)}
         st64.close()
-    if not args.topk and not args.no_topk_variant:
+    if not args.topk and not args.no_variants:
         # the same circuit with the partial (top-k) factorisation: a variant
         # beside the contract's number, not part of it
         log("partial-factorisation variant")
@@ -826,7 +826,7 @@ def main():
                                                      for r in gk)),
             "speedup_vs_full_svd": tk and (ms_step / 1000.0) / tk}
         stk.close()
-    if not args.no_topk_variant:
+    if not args.no_variants:
         # the same circuit in the layer-parallel gauge (Vidal form, Hastings
         # update): another variant beside the contract's number
         log("layer-parallel variant")
