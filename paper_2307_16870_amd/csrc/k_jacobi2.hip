@@ -283,29 +283,91 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         }
         return qq < nc;
     };
-    // rotation of pair slot `sl` at `step` from the current G (slot < npairs)
-    auto make_rot = [&](int sl, int step, int cnt_slot) -> RotRec<T> {
+    // rotation of pair slot `sl` at `step` from the diagonal entries al, be of
+    // its columns p, q and the entry ga = G[p][q].  The record carries al and
+    // be whether or not the pair rotates (the chained formation below follows
+    // the diagonal through them).
+    auto form_rot = [&](int sl, int step, T al, T be, cx<T> ga) -> RotRec<T> {
         int p, q;
         RotRec<T> r;
-        r.s = r.gm = r.tg = r.al = r.be = T(0);
+        r.s = r.gm = r.tg = T(0);
+        r.al = al;
+        r.be = be;
         r.e = mk<T>(T(1), T(0));
         r.on = 0;
         if (slot_pq(sl, step, p, q)) {
-            const T al = G[p][p].x, be = G[q][q].x;
-            const cx<T> ga = G[p][q];
             JRot<T> rt;
             if (jacobi_rotation(al, be, ga, tol, rt)) {
                 r.s = rt.s;
                 r.gm = rt.gm;
                 r.e = rt.e;
                 r.tg = rt.tg;
-                r.al = al;
-                r.be = be;
                 r.on = 1;
-                atomicAdd(&nrot_sh[cnt_slot], 1);
             }
         }
         return r;
+    };
+    // the same from the current G (p, q of every slot index rows of G)
+    auto make_rot = [&](int sl, int step) -> RotRec<T> {
+        int p, q;
+        slot_pq(sl, step, p, q);
+        return form_rot(sl, step, G[p][p].x, G[q][q].x, G[p][q]);
+    };
+    // Every caller of make_rot / form_rot is a thread tid < npairs <= 32, all
+    // in the first wave: the rotations of a step are counted by one ballot.
+    auto count_rot = [&](bool on, int cnt_slot) {
+        const unsigned long long bal = __ballot(on);
+        if (tid == 0) nrot_sh[cnt_slot] += __popcll(bal);
+    };
+    // G <- M^H G M on the 2x2 block (row pair a, column pair b), a <= b; block
+    // (b, a) is its conjugate transpose, written alongside.  x01, x10 return
+    // the block's entries (p_a, q_b) and (q_a, p_b) after the update.
+    auto block_update = [&](int a, int b, int step, const RotRec<T> *rec, cx<T> &x01,
+                            cx<T> &x10) {
+        int pa, qa, pb, qb;
+        slot_pq(a, step, pa, qa);
+        slot_pq(b, step, pb, qb);
+        const RotRec<T> ra = rec[a], rb = rec[b];
+        cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g10 = G[qa][pb], g11 = G[qa][qb];
+        x01 = g01;
+        x10 = g10;
+        if (!ra.on && !rb.on) return;
+        if (a == b) {  // rotated pair: exact diagonal
+            G[pa][qa] = zero_cx<T>();
+            G[qa][pa] = zero_cx<T>();
+            G[pa][pa] = mk<T>(ra.al - ra.tg, T(0));
+            G[qa][qa] = mk<T>(ra.be + ra.tg, T(0));
+            x01 = x10 = zero_cx<T>();
+            return;
+        }
+        const bool va = qa < nc, vb = qb < nc;
+        if (!vb) g01 = g11 = zero_cx<T>();
+        if (!va) g10 = g11 = zero_cx<T>();
+        if (rb.on) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
+            rot_pair(g00, rb.e * g01, rb.s, rb.gm, g00, g01);
+            rot_pair(g10, rb.e * g11, rb.s, rb.gm, g10, g11);
+        }
+        if (ra.on) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
+            const cx<T> ec = conj(ra.e);
+            rot_pair(g00, ec * g10, ra.s, ra.gm, g00, g10);
+            rot_pair(g01, ec * g11, ra.s, ra.gm, g01, g11);
+        }
+        x01 = g01;
+        x10 = g10;
+        G[pa][pb] = g00;
+        G[pb][pa] = conj(g00);
+        if (vb) {
+            G[pa][qb] = g01;
+            G[qb][pa] = conj(g01);
+        }
+        if (va) {
+            G[qa][pb] = g10;
+            G[pb][qa] = conj(g10);
+        }
+        if (va && vb) {
+            G[qa][qb] = g11;
+            G[qb][qa] = conj(g11);
+        }
     };
     // Inter-block order: slot sl always rotates column sl of block a against
     // column na + (sl + step) mod w of block b, so J's columns are held in
@@ -345,86 +407,113 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         }
         need = __syncthreads_or(any) != 0;
     }
+    // J <- J M for the rotations of one step
+    auto j_update = [&](int step, const RotRec<T> *rec) {
+        if constexpr (REGJ) {
+            const RotRec<T> rb = rec[sl_j < npairs ? sl_j : 0];
+            const bool on = sl_j < npairs && rb.on;
+#pragma unroll
+            for (int i = 0; i < RI; ++i) {
+                if (on) rot_pair(ja[i], rb.e * jb[i], rb.s, rb.gm, ja[i], jb[i]);
+                jb[i] = mk<T>(__shfl(jb[i].x, src_j), __shfl(jb[i].y, src_j));
+            }
+        } else {
+            for (int e = tid; e < NP * NC; e += NTH) {
+                const int b = e / NC, row = e % NC;
+                if (b >= npairs || row >= nc) continue;
+                int p, q;
+                slot_pq(b, step, p, q);
+                const RotRec<T> rb = rec[b];
+                const cx<T> jp = J[row][p], jq = J[row][q];
+                if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
+            }
+        }
+    };
+    // Chained formation (inter-block order with w = NP): at step k + 1 slot s
+    // pairs column s of block a with the block-b column that slot s + 1 held
+    // at step k.  Its entries are the diagonal of column s (al - tg if slot s
+    // rotated at step k, else al), that of slot s + 1's block-b column (be +
+    // tg, else be) and entry (p_s, q_{s+1}) of the 2x2 block (s, s + 1) just
+    // updated.  The first wave owns the blocks (s, s + 1 mod w) and the
+    // diagonal blocks, so the thread that updates block (s, s + 1) forms the
+    // next rotation of slot s from values it holds: one barrier per step, and
+    // the inputs of every rotation are the values the unchained order reads
+    // back from G.
+    const bool chain = inter && w == NP && NP >= 4;
+    constexpr int NU = NP * (NP + 1) / 2;
+    constexpr int G0 = (2 * NP + 63) / 64 * 64;  // first thread of the other blocks
     int first = 0;
     if (need && nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
             const int slot = isw & 1;
-            if (tid < npairs) rec_[0][tid] = make_rot(tid, 0, slot);
+            if (tid < npairs) {
+                const RotRec<T> r = make_rot(tid, 0);
+                rec_[0][tid] = r;
+                count_rot(r.on, slot);
+            }
             __syncthreads();
-            for (int step = 0; step < nsteps; ++step) {
-                const RotRec<T> *rec = rec_[step & 1];
-                // G <- M^H G M on 2x2 blocks (row pair a, column pair b), a <= b only:
-                // each block needs only its own four entries, and block (b, a) is
-                // its conjugate transpose, written alongside.  The a <= b blocks
-                // are packed (tab_) so that only as many waves as needed work.
-                for (int e = tid; e < NP * (NP + 1) / 2; e += NTH) {
-                    const int ab = tab_[e], a = ab >> 8, b = ab & 255;
-                    if (b >= npairs) continue;
-                    int pa, qa, pb, qb;
-                    slot_pq(a, step, pa, qa);
-                    slot_pq(b, step, pb, qb);
-                    const RotRec<T> ra = rec[a], rb = rec[b];
-                    cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g10 = G[qa][pb], g11 = G[qa][qb];
-                    if (!ra.on && !rb.on) continue;
-                    if (a == b) {  // rotated pair: exact diagonal
-                        G[pa][qa] = zero_cx<T>();
-                        G[qa][pa] = zero_cx<T>();
-                        G[pa][pa] = mk<T>(ra.al - ra.tg, T(0));
-                        G[qa][qa] = mk<T>(ra.be + ra.tg, T(0));
-                        continue;
+            if (chain) {
+                for (int step = 0; step < nsteps; ++step) {
+                    const RotRec<T> *rec = rec_[step & 1];
+                    // one block per thread, chosen first, so that a wave runs a
+                    // single copy of the update
+                    int a = -1, b = -1;
+                    if (tid < NP) {
+                        const int s1 = tid + 1 == NP ? 0 : tid + 1;
+                        a = s1 != 0 ? tid : 0;
+                        b = s1 != 0 ? s1 : tid;
+                    } else if (tid < 2 * NP) {
+                        a = b = tid - NP;
+                    } else if (tid >= G0 && tid - G0 < NU) {
+                        const int ab = tab_[tid - G0];
+                        a = ab >> 8;
+                        b = ab & 255;
+                        if (b <= a + 1 || (a == 0 && b == NP - 1)) a = -1;
                     }
-                    const bool va = qa < nc, vb = qb < nc;
-                    if (!vb) g01 = g11 = zero_cx<T>();
-                    if (!va) g10 = g11 = zero_cx<T>();
-                    if (rb.on) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
-                        rot_pair(g00, rb.e * g01, rb.s, rb.gm, g00, g01);
-                        rot_pair(g10, rb.e * g11, rb.s, rb.gm, g10, g11);
+                    cx<T> x01, x10;
+                    if (a >= 0) block_update(a, b, step, rec, x01, x10);
+                    if (tid < NP && step + 1 < nsteps) {
+                        const int s = tid, s1 = s + 1 == NP ? 0 : s + 1;
+                        const RotRec<T> r0 = rec[s], r1 = rec[s1];
+                        const T al = r0.on ? r0.al - r0.tg : r0.al;
+                        const T be = r1.on ? r1.be + r1.tg : r1.be;
+                        const RotRec<T> r =
+                            form_rot(s, step + 1, al, be, s1 != 0 ? x01 : conj(x10));
+                        rec_[(step + 1) & 1][s] = r;
+                        count_rot(r.on, slot);
                     }
-                    if (ra.on) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
-                        const cx<T> ec = conj(ra.e);
-                        rot_pair(g00, ec * g10, ra.s, ra.gm, g00, g10);
-                        rot_pair(g01, ec * g11, ra.s, ra.gm, g01, g11);
+                    if constexpr (NTH < G0 + NU) {  // blocks beyond one per thread
+                        for (int e = tid - G0 + NTH; e < NU; e += NTH) {
+                            const int ab = tab_[e], a2 = ab >> 8, b2 = ab & 255;
+                            if (b2 <= a2 + 1 || (a2 == 0 && b2 == NP - 1)) continue;
+                            block_update(a2, b2, step, rec, x01, x10);
+                        }
                     }
-                    G[pa][pb] = g00;
-                    G[pb][pa] = conj(g00);
-                    if (vb) {
-                        G[pa][qb] = g01;
-                        G[qb][pa] = conj(g01);
-                    }
-                    if (va) {
-                        G[qa][pb] = g10;
-                        G[pb][qa] = conj(g10);
-                    }
-                    if (va && vb) {
-                        G[qa][qb] = g11;
-                        G[qb][qa] = conj(g11);
-                    }
+                    j_update(step, rec);
+                    __syncthreads();
                 }
-                __syncthreads();
-                // the next step's rotations need only the updated G: they are formed
-                // while this step's rotations are applied to J (J <- J M)
-                if (step + 1 < nsteps && tid < npairs)
-                    rec_[(step + 1) & 1][tid] = make_rot(tid, step + 1, slot);
-                if constexpr (REGJ) {
-                    const RotRec<T> rb = rec[sl_j < npairs ? sl_j : 0];
-                    const bool on = sl_j < npairs && rb.on;
-#pragma unroll
-                    for (int i = 0; i < RI; ++i) {
-                        if (on) rot_pair(ja[i], rb.e * jb[i], rb.s, rb.gm, ja[i], jb[i]);
-                        jb[i] = mk<T>(__shfl(jb[i].x, src_j), __shfl(jb[i].y, src_j));
+            } else {
+                for (int step = 0; step < nsteps; ++step) {
+                    const RotRec<T> *rec = rec_[step & 1];
+                    // the a <= b blocks are packed (tab_) so that only as many
+                    // waves as needed work
+                    for (int e = tid; e < NU; e += NTH) {
+                        const int ab = tab_[e], a = ab >> 8, b = ab & 255;
+                        if (b >= npairs) continue;
+                        cx<T> x01, x10;
+                        block_update(a, b, step, rec, x01, x10);
                     }
-                } else {
-                    for (int e = tid; e < NP * NC; e += NTH) {
-                        const int b = e / NC, row = e % NC;
-                        if (b >= npairs || row >= nc) continue;
-                        int p, q;
-                        slot_pq(b, step, p, q);
-                        const RotRec<T> rb = rec[b];
-                        const cx<T> jp = J[row][p], jq = J[row][q];
-                        if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
+                    __syncthreads();
+                    // the next step's rotations need only the updated G: they are
+                    // formed while this step's rotations are applied to J
+                    if (step + 1 < nsteps && tid < npairs) {
+                        const RotRec<T> r = make_rot(tid, step + 1);
+                        rec_[(step + 1) & 1][tid] = r;
+                        count_rot(r.on, slot);
                     }
+                    j_update(step, rec);
+                    __syncthreads();
                 }
-                __syncthreads();
             }
             const int nr = nrot_sh[slot];
             if (isw == 0) first = nr;
