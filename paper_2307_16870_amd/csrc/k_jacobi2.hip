@@ -70,6 +70,21 @@ __device__ __forceinline__ bool pair_unchanged(const int *stamp, int nb, int rnd
 
 constexpr int JRS = 64;  // rows staged in LDS per step
 
+// A rotation as the block and J updates read it (16 bytes in FP32): gm < 0
+// marks a pair that does not rotate (1 - cos is never negative).
+template <typename T>
+struct alignas(16) RotP {
+    T s, gm;  // sin, 1 - cos
+    cx<T> e;  // phase conj(g) / |g|
+};
+// The diagonal entries of the pair's columns before the step, the shift t |g|
+// they take when it rotates, and whether it does.
+template <typename T>
+struct alignas(16) RotD {
+    T al, be, tg;
+    int on;
+};
+
 // Load rows [r0, r0+JRS) of the owned columns into split real/imag LDS planes,
 // zero-padding rows >= r_end and columns >= nc.
 // All loads of a thread are issued before the first LDS write, so their
@@ -209,7 +224,8 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     __shared__ cx<T> G[NC][NC + 1];
     __shared__ cx<T> J[NC][NC + 1];
     static_assert((NP & (NP - 1)) == 0 && NP <= 256, "block pair width must be a power of 2");
-    __shared__ RotRec<T> rec_[2][NP];  // this step's rotations and the next step's
+    __shared__ RotP<T> rp_[2][NP];  // this step's rotations and the next step's
+    __shared__ RotD<T> rd_[2][NP];
     __shared__ unsigned short tab_[NP * (NP + 1) / 2];  // packed (a, b), a <= b
     __shared__ int cols[NC];
     __shared__ int nrot_sh[2];
@@ -319,35 +335,49 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         const unsigned long long bal = __ballot(on);
         if (tid == 0) nrot_sh[cnt_slot] += __popcll(bal);
     };
+    auto store_rot = [&](int buf, int sl, const RotRec<T> &r) {
+        RotP<T> rp;
+        rp.s = r.s;
+        rp.gm = r.on ? r.gm : T(-1);
+        rp.e = r.e;
+        rp_[buf][sl] = rp;
+        RotD<T> rd;
+        rd.al = r.al;
+        rd.be = r.be;
+        rd.tg = r.tg;
+        rd.on = r.on;
+        rd_[buf][sl] = rd;
+    };
     // G <- M^H G M on the 2x2 block (row pair a, column pair b), a <= b; block
     // (b, a) is its conjugate transpose, written alongside.  x01, x10 return
     // the block's entries (p_a, q_b) and (q_a, p_b) after the update.
-    auto block_update = [&](int a, int b, int step, const RotRec<T> *rec, cx<T> &x01,
-                            cx<T> &x10) {
+    auto block_update = [&](int a, int b, int step, int buf, cx<T> &x01, cx<T> &x10) {
         int pa, qa, pb, qb;
         slot_pq(a, step, pa, qa);
         slot_pq(b, step, pb, qb);
-        const RotRec<T> ra = rec[a], rb = rec[b];
+        const RotP<T> ra = rp_[buf][a], rb = rp_[buf][b];
+        const bool ona = ra.gm >= T(0), onb = rb.gm >= T(0);
         cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g10 = G[qa][pb], g11 = G[qa][qb];
         x01 = g01;
         x10 = g10;
-        if (!ra.on && !rb.on) return;
+        if (!ona && !onb) return;
         if (a == b) {  // rotated pair: exact diagonal
+            const RotD<T> d = rd_[buf][a];
             G[pa][qa] = zero_cx<T>();
             G[qa][pa] = zero_cx<T>();
-            G[pa][pa] = mk<T>(ra.al - ra.tg, T(0));
-            G[qa][qa] = mk<T>(ra.be + ra.tg, T(0));
+            G[pa][pa] = mk<T>(d.al - d.tg, T(0));
+            G[qa][qa] = mk<T>(d.be + d.tg, T(0));
             x01 = x10 = zero_cx<T>();
             return;
         }
         const bool va = qa < nc, vb = qb < nc;
         if (!vb) g01 = g11 = zero_cx<T>();
         if (!va) g10 = g11 = zero_cx<T>();
-        if (rb.on) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
+        if (onb) {  // columns: [x0, x1] = [g0, g1] [[c, s], [-s e, c e]]
             rot_pair(g00, rb.e * g01, rb.s, rb.gm, g00, g01);
             rot_pair(g10, rb.e * g11, rb.s, rb.gm, g10, g11);
         }
-        if (ra.on) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
+        if (ona) {  // rows: [r0; r1] = [[c, -s e*], [s, c e*]] [g0; g1]
             const cx<T> ec = conj(ra.e);
             rot_pair(g00, ec * g10, ra.s, ra.gm, g00, g10);
             rot_pair(g01, ec * g11, ra.s, ra.gm, g01, g11);
@@ -375,16 +405,23 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     // and the block-b column it meets at the current step, and after each
     // step takes the block-b values of slot (sl + 1) mod w.  After whole
     // inner sweeps (w steps each) every block-b value is back at its slot.
-    constexpr int RGROUPS = NTH / NP;                 // row groups of NP lanes
+    // The first wave, which forms the rotations, holds no rows of J when the
+    // other waves can hold them all at 4 rows per thread (FP32: in FP64 the
+    // extra rows spill registers).
+    constexpr int JG0 = (INTER != 0 && sizeof(T) == 4 && NTH >= 256 && NP <= 64 &&
+                         (NC + NTH / NP - 64 / NP - 1) / (NTH / NP - 64 / NP) <= 4)
+                            ? 64 / NP
+                            : 0;
+    constexpr int RGROUPS = NTH / NP - JG0;           // row groups of NP lanes
     constexpr int RI = (NC + RGROUPS - 1) / RGROUPS;  // rows per thread
     constexpr bool REGJ = INTER != 0 && NP <= 64 && RGROUPS >= 1 && RI <= 4;
-    const int sl_j = tid % NP, grp_j = tid / NP;
+    const int sl_j = tid % NP, grp_j = tid / NP - JG0;  // grp_j < 0: the first wave
     cx<T> ja[RI], jb[RI];
     int src_j = tid % 64;
     if constexpr (REGJ) {
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
-            const int row = grp_j + i * RGROUPS;
+            const int row = grp_j < 0 ? -1 : grp_j + i * RGROUPS;
             ja[i] = mk<T>(sl_j < na && row == sl_j ? T(1) : T(0), T(0));
             jb[i] = mk<T>(sl_j < w && row == na + sl_j ? T(1) : T(0), T(0));
         }
@@ -408,10 +445,11 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         need = __syncthreads_or(any) != 0;
     }
     // J <- J M for the rotations of one step
-    auto j_update = [&](int step, const RotRec<T> *rec) {
+    auto j_update = [&](int step, int buf) {
         if constexpr (REGJ) {
-            const RotRec<T> rb = rec[sl_j < npairs ? sl_j : 0];
-            const bool on = sl_j < npairs && rb.on;
+            if (grp_j < 0) return;  // uniform over the first wave
+            const RotP<T> rb = rp_[buf][sl_j < npairs ? sl_j : 0];
+            const bool on = sl_j < npairs && rb.gm >= T(0);
 #pragma unroll
             for (int i = 0; i < RI; ++i) {
                 if (on) rot_pair(ja[i], rb.e * jb[i], rb.s, rb.gm, ja[i], jb[i]);
@@ -423,9 +461,9 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                 if (b >= npairs || row >= nc) continue;
                 int p, q;
                 slot_pq(b, step, p, q);
-                const RotRec<T> rb = rec[b];
+                const RotP<T> rb = rp_[buf][b];
                 const cx<T> jp = J[row][p], jq = J[row][q];
-                if (rb.on) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
+                if (rb.gm >= T(0)) rot_pair(jp, rb.e * jq, rb.s, rb.gm, J[row][p], J[row][q]);
             }
         }
     };
@@ -442,19 +480,21 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     const bool chain = inter && w == NP && NP >= 4;
     constexpr int NU = NP * (NP + 1) / 2;
     constexpr int G0 = (2 * NP + 63) / 64 * 64;  // first thread of the other blocks
+    // the diagonal blocks go to the last wave when it has nothing else to update
+    constexpr int D0 = NTH >= G0 + NU + 64 ? NTH - 64 : NP;
     int first = 0;
     if (need && nc >= 2 && (!inter || (na > 0 && nc > na))) {
         for (int isw = 0; isw < inner_max; ++isw) {
             const int slot = isw & 1;
             if (tid < npairs) {
                 const RotRec<T> r = make_rot(tid, 0);
-                rec_[0][tid] = r;
+                store_rot(0, tid, r);
                 count_rot(r.on, slot);
             }
             __syncthreads();
             if (chain) {
                 for (int step = 0; step < nsteps; ++step) {
-                    const RotRec<T> *rec = rec_[step & 1];
+                    const int buf = step & 1;
                     // one block per thread, chosen first, so that a wave runs a
                     // single copy of the update
                     int a = -1, b = -1;
@@ -462,8 +502,8 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                         const int s1 = tid + 1 == NP ? 0 : tid + 1;
                         a = s1 != 0 ? tid : 0;
                         b = s1 != 0 ? s1 : tid;
-                    } else if (tid < 2 * NP) {
-                        a = b = tid - NP;
+                    } else if (tid >= D0 && tid < D0 + NP) {
+                        a = b = tid - D0;
                     } else if (tid >= G0 && tid - G0 < NU) {
                         const int ab = tab_[tid - G0];
                         a = ab >> 8;
@@ -471,47 +511,47 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
                         if (b <= a + 1 || (a == 0 && b == NP - 1)) a = -1;
                     }
                     cx<T> x01, x10;
-                    if (a >= 0) block_update(a, b, step, rec, x01, x10);
+                    if (a >= 0) block_update(a, b, step, buf, x01, x10);
                     if (tid < NP && step + 1 < nsteps) {
                         const int s = tid, s1 = s + 1 == NP ? 0 : s + 1;
-                        const RotRec<T> r0 = rec[s], r1 = rec[s1];
+                        const RotD<T> r0 = rd_[buf][s], r1 = rd_[buf][s1];
                         const T al = r0.on ? r0.al - r0.tg : r0.al;
                         const T be = r1.on ? r1.be + r1.tg : r1.be;
                         const RotRec<T> r =
                             form_rot(s, step + 1, al, be, s1 != 0 ? x01 : conj(x10));
-                        rec_[(step + 1) & 1][s] = r;
+                        store_rot(buf ^ 1, s, r);
                         count_rot(r.on, slot);
                     }
                     if constexpr (NTH < G0 + NU) {  // blocks beyond one per thread
                         for (int e = tid - G0 + NTH; e < NU; e += NTH) {
                             const int ab = tab_[e], a2 = ab >> 8, b2 = ab & 255;
                             if (b2 <= a2 + 1 || (a2 == 0 && b2 == NP - 1)) continue;
-                            block_update(a2, b2, step, rec, x01, x10);
+                            block_update(a2, b2, step, buf, x01, x10);
                         }
                     }
-                    j_update(step, rec);
+                    j_update(step, buf);
                     __syncthreads();
                 }
             } else {
                 for (int step = 0; step < nsteps; ++step) {
-                    const RotRec<T> *rec = rec_[step & 1];
+                    const int buf = step & 1;
                     // the a <= b blocks are packed (tab_) so that only as many
                     // waves as needed work
                     for (int e = tid; e < NU; e += NTH) {
                         const int ab = tab_[e], a = ab >> 8, b = ab & 255;
                         if (b >= npairs) continue;
                         cx<T> x01, x10;
-                        block_update(a, b, step, rec, x01, x10);
+                        block_update(a, b, step, buf, x01, x10);
                     }
                     __syncthreads();
                     // the next step's rotations need only the updated G: they are
                     // formed while this step's rotations are applied to J
                     if (step + 1 < nsteps && tid < npairs) {
                         const RotRec<T> r = make_rot(tid, step + 1);
-                        rec_[(step + 1) & 1][tid] = r;
+                        store_rot(buf ^ 1, tid, r);
                         count_rot(r.on, slot);
                     }
-                    j_update(step, rec);
+                    j_update(step, buf);
                     __syncthreads();
                 }
             }
@@ -526,7 +566,7 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
             const int row = grp_j + i * RGROUPS;
-            if (row >= NC) continue;
+            if (grp_j < 0 || row >= NC) continue;
             if (sl_j < na) J[row][sl_j] = ja[i];
             if (sl_j < w && na + sl_j < NC) J[row][na + sl_j] = jb[i];
         }
