@@ -70,6 +70,24 @@ __device__ __forceinline__ bool pair_unchanged(const int *stamp, int nb, int rnd
 
 constexpr int JRS = 64;  // rows staged in LDS per step
 
+// True whenever jacobi_rotation would rotate the pair (it may also be true
+// when it would not).  FP32 data: |g|^2 > tol^2 al be in FP64 with a relative
+// margin of 1e-9 toward rotating, far wider than the error of the refined
+// square roots of the exact test, and no square root or reciprocal on the
+// way; squares of FP32 values neither overflow nor underflow in FP64.  FP64
+// data take the exact test.
+template <typename T>
+__device__ __forceinline__ bool may_rotate(T al, T be, cx<T> ga, T tol) {
+    if constexpr (sizeof(T) == 4) {
+        const double gx = ga.x, gy = ga.y, g2 = gx * gx + gy * gy;
+        const double ab = (double)al * (double)be, t = tol;
+        return g2 > 0.0 && ab >= 0.0 && (ab == 0.0 || g2 > t * t * ab * (1.0 - 1e-9));
+    } else {
+        JRot<T> rt;
+        return jacobi_rotation(al, be, ga, tol, rt);
+    }
+}
+
 // A rotation as the block and J updates read it (16 bytes in FP32): gm < 0
 // marks a pair that does not rotate (1 - cos is never negative).
 template <typename T>
@@ -437,10 +455,7 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         for (int e = tid; e < NC * NC && !any; e += NTH) {
             const int p = e / NC, q = e % NC;
             const bool cand = inter ? (p < na && q >= na && q < nc) : (p < q && q < nc);
-            if (cand) {
-                JRot<T> rt;
-                any = jacobi_rotation(G[p][p].x, G[q][q].x, G[p][q], tol, rt);
-            }
+            if (cand) any = may_rotate(G[p][p].x, G[q][q].x, G[p][q], tol);
         }
         need = __syncthreads_or(any) != 0;
     }
