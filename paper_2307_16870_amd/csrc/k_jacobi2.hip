@@ -369,20 +369,26 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     // G <- M^H G M on the 2x2 block (row pair a, column pair b), a <= b; block
     // (b, a) is its conjugate transpose, written alongside.  x01, x10 return
     // the block's entries (p_a, q_b) and (q_a, p_b) after the update.
+    // Inter-block order: rows p (block a) against columns q (block b) are kept
+    // in the upper-right quadrant only, an entry (q, p) being read as the
+    // conjugate of (p, q), and the lower triangle of the block-a quadrant is
+    // not written: no step and no rotation reads it (the p indices of a block
+    // are increasing, and rotations read (p, p), (q, q) and (p, q)).
     auto block_update = [&](int a, int b, int step, int buf, cx<T> &x01, cx<T> &x10) {
         int pa, qa, pb, qb;
         slot_pq(a, step, pa, qa);
         slot_pq(b, step, pb, qb);
         const RotP<T> ra = rp_[buf][a], rb = rp_[buf][b];
         const bool ona = ra.gm >= T(0), onb = rb.gm >= T(0);
-        cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g10 = G[qa][pb], g11 = G[qa][qb];
+        cx<T> g00 = G[pa][pb], g01 = G[pa][qb], g11 = G[qa][qb];
+        cx<T> g10 = inter ? conj(G[pb][qa]) : G[qa][pb];
         x01 = g01;
         x10 = g10;
         if (!ona && !onb) return;
         if (a == b) {  // rotated pair: exact diagonal
             const RotD<T> d = rd_[buf][a];
             G[pa][qa] = zero_cx<T>();
-            G[qa][pa] = zero_cx<T>();
+            if (!inter) G[qa][pa] = zero_cx<T>();
             G[pa][pa] = mk<T>(d.al - d.tg, T(0));
             G[qa][qa] = mk<T>(d.be + d.tg, T(0));
             x01 = x10 = zero_cx<T>();
@@ -403,13 +409,13 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         x01 = g01;
         x10 = g10;
         G[pa][pb] = g00;
-        G[pb][pa] = conj(g00);
+        if (!inter) G[pb][pa] = conj(g00);
         if (vb) {
             G[pa][qb] = g01;
-            G[qb][pa] = conj(g01);
+            if (!inter) G[qb][pa] = conj(g01);
         }
         if (va) {
-            G[qa][pb] = g10;
+            if (!inter) G[qa][pb] = g10;
             G[pb][qa] = conj(g10);
         }
         if (va && vb) {
