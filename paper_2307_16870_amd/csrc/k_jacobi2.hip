@@ -253,33 +253,73 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
         return;
     }
     const int nc = pair_columns(pair, rnd, nb, w, n, cols, tid, NTH);
-    // sum the partial Gram tiles (upper triangle) in a fixed order
+    // Sum the partial Gram tiles (upper triangle) in a fixed order per entry.
+    // Rows r and NC - 1 - r together hold NC + 1 entries of the triangle, so
+    // entry e of the NC/2 x (NC + 1) arrangement spreads the triangle evenly
+    // over the threads; each thread issues the chunk loads of two entries
+    // before summing either.
     const cx<T> *src = partial + (size_t)pair * nchunks * NC * NC;
+    constexpr int NUT = (NC / 2) * (NC + 1);
+    auto tri = [&](int e, int &p, int &q) {
+        const int r = e / (NC + 1), c = e % (NC + 1);
+        if (c < NC - r) {
+            p = r;
+            q = r + c;
+        } else {
+            p = NC - 1 - r;
+            q = p + (c - (NC - r));
+        }
+    };
+    auto put = [&](int p, int q, double sx, double sy) {
+        if (p != q) {
+            G[p][q] = mk<T>((T)sx, (T)sy);
+            G[q][p] = mk<T>((T)sx, (T)-sy);
+        } else {
+            G[p][p] = mk<T>((T)sx, T(0));
+        }
+    };
+    for (int e0 = tid; e0 < NUT; e0 += 2 * NTH) {
+        const int e1 = e0 + NTH;
+        const bool two = e1 < NUT;
+        int p0, q0, p1 = 0, q1 = 0;
+        tri(e0, p0, q0);
+        if (two) tri(e1, p1, q1);
+        const size_t o0 = (size_t)p0 * NC + q0, o1 = (size_t)p1 * NC + q1;
+        double sx0 = 0.0, sy0 = 0.0, sx1 = 0.0, sy1 = 0.0;
+        int c = 0;
+        for (; c + 8 <= nchunks; c += 8) {
+            cx<T> v0[8], v1[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v0[j] = src[(size_t)(c + j) * NC * NC + o0];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v1[j] = two ? src[(size_t)(c + j) * NC * NC + o1] : zero_cx<T>();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sx0 += (double)v0[j].x;
+                sy0 += (double)v0[j].y;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sx1 += (double)v1[j].x;
+                sy1 += (double)v1[j].y;
+            }
+        }
+        for (; c < nchunks; ++c) {
+            const cx<T> v0 = src[(size_t)c * NC * NC + o0];
+            sx0 += (double)v0.x;
+            sy0 += (double)v0.y;
+            if (two) {
+                const cx<T> v1 = src[(size_t)c * NC * NC + o1];
+                sx1 += (double)v1.x;
+                sy1 += (double)v1.y;
+            }
+        }
+        put(p0, q0, sx0, sy0);
+        if (two) put(p1, q1, sx1, sy1);
+    }
     for (int e = tid; e < NC * NC; e += NTH) {
         const int p = e / NC, q = e % NC;
-        if (p <= q) {
-            // chunks summed in order, eight loads in flight at a time
-            double sx = 0.0, sy = 0.0;
-            int c = 0;
-            for (; c + 8 <= nchunks; c += 8) {
-                cx<T> v[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = src[(size_t)(c + j) * NC * NC + e];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    sx += (double)v[j].x;
-                    sy += (double)v[j].y;
-                }
-            }
-            for (; c < nchunks; ++c) {
-                const cx<T> v = src[(size_t)c * NC * NC + e];
-                sx += (double)v.x;
-                sy += (double)v.y;
-            }
-            G[p][q] = mk<T>((T)sx, (T)sy);
-            if (p != q) G[q][p] = mk<T>((T)sx, (T)-sy);
-            else G[p][p] = mk<T>((T)sx, T(0));
-        }
         J[p][q] = mk<T>(p == q ? T(1) : T(0), T(0));
     }
     if (tid < 2) nrot_sh[tid] = 0;
