@@ -533,9 +533,10 @@ __global__ __launch_bounds__(NTH) void k_jeig(const cx<T> *__restrict__ partial,
     // at step k.  Its entries are the diagonal of column s (al - tg if slot s
     // rotated at step k, else al), that of slot s + 1's block-b column (be +
     // tg, else be) and entry (p_s, q_{s+1}) of the 2x2 block (s, s + 1) just
-    // updated.  The first wave owns the blocks (s, s + 1 mod w) and the
-    // diagonal blocks, so the thread that updates block (s, s + 1) forms the
-    // next rotation of slot s from values it holds: one barrier per step, and
+    // updated.  The first wave owns the blocks (s, s + 1 mod w), so the
+    // thread that updates block (s, s + 1) forms the next rotation of slot s
+    // from values it holds (the diagonal values from the rotation records of
+    // slots s and s + 1): one barrier per step, and
     // the inputs of every rotation are the values the unchained order reads
     // back from G.
     const bool chain = inter && w == NP && NP >= 4;
